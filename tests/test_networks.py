@@ -1,0 +1,77 @@
+"""The comparator networks the kernels use, checked with the oracle's
+exhaustive 0-1 checker (Table 1 counts; the 0-1 principle)."""
+import re
+
+import pytest
+
+import oracle
+from paper_2409_03970_amd import netgen
+
+
+def _table1(golden_dir):
+    rows = {}
+    with open(f"{golden_dir}/table1_comparators.txt") as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                n, bit, oe, lo, hi = map(int, line.split())
+                rows[n] = (bit, oe, lo, hi)
+    return rows
+
+
+@pytest.mark.parametrize("n", [4, 8, 16, 32])
+def test_generated_counts_match_table1(golden_dir, n):
+    bit, oe, lo, hi = _table1(golden_dir)[n]
+    assert len(netgen.bitonic(n)) == bit
+    assert len(netgen.oddeven(n)) == oe
+
+
+@pytest.mark.parametrize("n", [4, 8, 16])
+def test_generated_symmetric_networks_sort(n):
+    assert oracle.network_failures01(netgen.bitonic(n), n) == 0
+    assert oracle.network_failures01(netgen.oddeven(n), n) == 0
+
+
+def test_column_network_16_is_within_table1_asymmetric_range(golden_dir):
+    bit, oe, lo, hi = _table1(golden_dir)[16]
+    net = netgen.column_network(16)
+    assert lo <= len(net) <= hi
+    assert len(net) < oe < bit
+    assert oracle.network_failures01(net, 16) == 0
+    # depth: ten layers, each touching every wire at most once
+    for layer in netgen.BEST16:
+        wires = [w for c in layer for w in c]
+        assert len(wires) == len(set(wires))
+    assert len(netgen.BEST16) == 10
+
+
+@pytest.mark.parametrize("R", [4, 8, 16])
+def test_column_networks_sort_all_01_inputs(R):
+    assert oracle.network_failures01(netgen.column_network(R), R) == 0
+
+
+def test_column_network_32_sorts_all_01_inputs():
+    # 2^32 inputs, bit-sliced: a few seconds
+    net = netgen.column_network(32)
+    assert len(net) == 191
+    assert oracle.network_failures01(net, 32) == 0
+
+
+@pytest.mark.parametrize("R", [8, 16])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_wave_merge_levels_merge_all_sorted_halves(R, k):
+    comps = netgen.wave_merge_level(R, k)
+    s = R << k
+    # the level acts on disjoint runs of s keys; check the first and the last
+    for base in (0, R * 64 - s):
+        sub = [(a - base, b - base) for a, b in comps if base <= a < base + s]
+        assert all(0 <= b - base < s for a, b in comps if base <= a < base + s)
+        assert oracle.merging_network_failures01(sub, s // 2, s // 2) == 0
+
+
+def test_header_matches_generator():
+    text = open(netgen.header_path()).read()
+    assert text == netgen.render_header()
+    for R in (4, 8, 16, 32):
+        m = re.search(rf"HVMS_NET{R}\[\d+\] = \{{([^}}]*)\}}", text)
+        vals = [int(x) for x in m.group(1).replace(" ", "").split(",")]
+        assert list(zip(vals[::2], vals[1::2])) == netgen.column_network(R)
