@@ -1,0 +1,218 @@
+/*
+ * hvms.h -- C ABI of the MI355X (gfx950) hybrid vectorized merge sort.
+ *
+ * The library implements the hot path of "A Hybrid Vectorized Merge Sort on
+ * ARM NEON" (arXiv 2409.03970) as HIP kernels: a per-wavefront register sort
+ * (column sort by a few-comparator network, Sec. 2.3; cross-lane bitonic
+ * merges, Sec. 2.4), LDS-staged block merges, and global merge passes whose
+ * work is split at merge-path co-ranks (the load-balanced partitioning of the
+ * parallel merge, Sec. 2.1).
+ *
+ * Conventions shared by every entry point:
+ *  - All array pointers are DEVICE pointers owned by the caller.  The library
+ *    never allocates device memory; scratch space comes from a caller-owned
+ *    workspace whose size the matching *_workspace_bytes call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    work is enqueued on it asynchronously; nothing synchronises the host.
+ *  - Keys are signed 32-bit integers sorted ascending.  Pairs are ordered
+ *    lexicographically by (key, value), both signed, which equals a stable
+ *    sort by key when the values are the original indices.
+ *  - Input and output may be the same array (in-place sort); otherwise they
+ *    must not overlap each other or the workspace.
+ *  - Every call returns an hvms status.  Argument errors are found on the
+ *    host before anything is enqueued; HVMS_ERR_HIP reports a failed launch
+ *    (hvms_last_hip_error() gives the hipError_t).  Faults inside kernels
+ *    surface at the caller's next synchronisation of the stream.
+ *  - Calls are re-entrant as long as concurrent calls use distinct workspaces.
+ */
+#ifndef HVMS_H
+#define HVMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HVMS_OK = 0,
+    HVMS_ERR_INVALID_ARG = -1, /* null pointer with n > 0, n < 0, bad option   */
+    HVMS_ERR_WORKSPACE = -2,   /* workspace null, too small or misaligned      */
+    HVMS_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed   */
+    HVMS_ERR_UNSUPPORTED = -4  /* a tuning value the build has no kernel for   */
+};
+
+/* Co-rank search modes for the global merge passes. */
+enum {
+    HVMS_CORANK_BINARY = 0,  /* plain binary search on the merge path          */
+    HVMS_CORANK_LEARNED = 1, /* CDF-model prediction + exact bounded search     */
+    HVMS_CORANK_LINEAR = 2   /* d*|A|/(|A|+|B|) prediction + the same search    */
+};
+
+/*
+ * Tuning and mode options.  A NULL pointer, or 0 in a field, selects the
+ * built-in default for that field.
+ *   keys_per_lane   R, keys each lane sorts in VGPRs: 8, 16 or 32 (Sec. 2.2
+ *                   picks 16 registers for NEON; here R is a VGPR budget).
+ *   block_threads   threads per block-sort workgroup: 256, 512 or 1024.  The
+ *                   block tile is keys_per_lane * block_threads keys.
+ *   wave_levels     cross-lane merge levels inside a wavefront, 1..6, stored
+ *                   as value+1 (so 0 keeps the default); levels beyond it up
+ *                   to the block tile are merged in LDS.
+ *   merge_tile      keys per workgroup in a global merge pass: 2048..16384.
+ *   corank_mode     HVMS_CORANK_*.
+ *   cdf_params      device pointer to HVMS_CDF_PARAMS floats (learned mode).
+ *   radius_log2     learned/linear mode: the bounded search first brackets
+ *                   the prediction with +-2^radius_log2 and falls back to
+ *                   binary search when the co-rank lies outside (default 12).
+ *   stats           optional device array of HVMS_STATS_WORDS uint64 counters
+ *                   the co-rank kernels add to (see HVMS_STAT_*), or NULL.
+ *   events/n_events optional caller-owned hipEvent_t handles for tracing: a
+ *                   sort records events[0]/[1] around its block-sort kernel
+ *                   and events[2+2p]/[3+2p] around the merge kernel of pass p
+ *                   (as far as n_events reaches), on the call's stream.
+ */
+typedef struct hvms_options {
+    int32_t keys_per_lane;
+    int32_t block_threads;
+    int32_t wave_levels;
+    int32_t merge_tile;
+    int32_t corank_mode;
+    int32_t radius_log2;
+    const float *cdf_params;
+    unsigned long long *stats;
+    void *const *events;
+    int32_t n_events;
+} hvms_options;
+
+enum {
+    HVMS_STAT_CORANKS = 0,   /* co-ranks computed                            */
+    HVMS_STAT_PROBES = 1,    /* dependent probe pairs read from memory       */
+    HVMS_STAT_FALLBACKS = 2, /* bounded searches that fell back to binary    */
+    HVMS_STAT_ABS_ERR = 3,   /* sum of |prediction - co-rank|                */
+    HVMS_STAT_MAX_ERR = 4,   /* max |prediction - co-rank|                   */
+    HVMS_STATS_WORDS = 8
+};
+
+const char *hvms_status_string(int status);
+int hvms_last_hip_error(void);
+
+/* ------------------------------------------------------------------ sort */
+
+/* Bytes of workspace hvms_sort_i32 / hvms_sort_pairs_i32 need for n keys
+ * (pairs != 0 for key-value sorts).  Returns a negative status on error. */
+int64_t hvms_sort_workspace_bytes(int64_t n, int32_t pairs, const hvms_options *opt);
+
+/*
+ * Sort n keys: d_out[0..n) = ascending arrangement of d_in[0..n)  (Sec. 2.1).
+ *   d_in, d_out   device int32 arrays of n elements (may be equal).
+ *   d_ws/ws_bytes workspace, >= hvms_sort_workspace_bytes(n, 0, opt), 256-byte
+ *                 aligned.
+ * n == 0 is a no-op returning HVMS_OK.
+ */
+int hvms_sort_i32(const int32_t *d_in, int32_t *d_out, int64_t n, void *d_ws,
+                  size_t ws_bytes, void *stream, const hvms_options *opt);
+
+/* Sort n (key, value) pairs lexicographically (keys and values are separate
+ * int32 arrays; outputs may alias the matching inputs). */
+int hvms_sort_pairs_i32(const int32_t *d_keys_in, const int32_t *d_vals_in,
+                        int32_t *d_keys_out, int32_t *d_vals_out, int64_t n,
+                        void *d_ws, size_t ws_bytes, void *stream,
+                        const hvms_options *opt);
+
+/*
+ * Sort every run of 2^run_log2 consecutive keys independently (the last run
+ * may be shorter): the block stage alone, i.e. "every X elements in order"
+ * of Table 2 with X = 2^run_log2.  run_log2 must lie in
+ * [log2(keys_per_lane), log2(block tile)].  Uses no workspace.
+ */
+int hvms_sort_runs_i32(const int32_t *d_in, int32_t *d_out, int64_t n, int32_t run_log2,
+                       void *stream, const hvms_options *opt);
+
+/*
+ * One global merge pass: d_in holds consecutive sorted runs of run_len keys
+ * (the last may be shorter); d_out receives the merge of each pair of runs,
+ * i.e. sorted runs of 2*run_len.  run_len must be a power of two >= the merge
+ * tile.  d_in and d_out must not overlap.  Workspace as returned by
+ * hvms_merge_workspace_bytes.
+ */
+int64_t hvms_merge_workspace_bytes(int64_t n, int64_t run_len, const hvms_options *opt);
+int hvms_merge_pass_i32(const int32_t *d_in, int32_t *d_out, int64_t n, int64_t run_len,
+                        void *d_ws, size_t ws_bytes, void *stream,
+                        const hvms_options *opt);
+
+/*
+ * Merge-path co-ranks (Sec. 2.1 partitioning): for each diagonal d_diag[q]
+ * (0 <= d <= m + k) of the merge of sorted d_a[0..m) and d_b[0..k),
+ * d_out[q] = number of elements of A among the first d outputs of the merge
+ * that takes A first on ties.  The result is unique; opt->corank_mode only
+ * changes how it is searched.
+ */
+int hvms_corank_i32(const int32_t *d_a, int64_t m, const int32_t *d_b, int64_t k,
+                    const int64_t *d_diag, int64_t count, int64_t *d_out, void *stream,
+                    const hvms_options *opt);
+
+/* ------------------------------------------------------------- segmented */
+
+/*
+ * Segmented sort: for every s in [0, nseg) sort keys d_in[off[s] .. off[s+1])
+ * into d_out at the same positions.  d_offsets is a DEVICE array of nseg+1
+ * nondecreasing int64 offsets; n_total = off[nseg] and max_seg (an upper
+ * bound on the largest segment) are passed by the host.  Keys outside every
+ * segment are copied through unchanged only if they lie in [off[0], n_total).
+ * All segments are sorted by one persistent launch (plus binning and, for
+ * segments above the block tile, merge passes inside the same launch).
+ */
+int64_t hvms_segmented_workspace_bytes(int64_t n_total, int64_t nseg, int64_t max_seg,
+                                       int32_t pairs, const hvms_options *opt);
+int hvms_segmented_sort_i32(const int32_t *d_in, int32_t *d_out, const int64_t *d_offsets,
+                            int64_t nseg, int64_t n_total, int64_t max_seg, void *d_ws,
+                            size_t ws_bytes, void *stream, const hvms_options *opt);
+int hvms_segmented_sort_pairs_i32(const int32_t *d_keys_in, const int32_t *d_vals_in,
+                                  int32_t *d_keys_out, int32_t *d_vals_out,
+                                  const int64_t *d_offsets, int64_t nseg, int64_t n_total,
+                                  int64_t max_seg, void *d_ws, size_t ws_bytes,
+                                  void *stream, const hvms_options *opt);
+
+/* -------------------------------------------------------- learned co-rank */
+
+/* The CDF model F(x) ~ P(key <= x): an fp32 perceptron 1 -> 32 -> 32 -> 1
+ * with ReLU, input x = (key + 2^31) / 2^32.  Parameter layout (floats):
+ * W1[32] b1[32] W2[32][32] (row = output unit) b2[32] W3[32] b3[1]. */
+#define HVMS_CDF_PARAMS 1153
+
+/* y[i] = F(x[i]) for i < b.  Device arrays. */
+int hvms_cdf_forward(const float *d_params, const float *d_x, float *d_y, int64_t b,
+                     void *stream);
+
+/* Mean squared error of F on (x, t) and its gradient: d_grad[HVMS_CDF_PARAMS],
+ * d_loss[1].  Reductions are deterministic (fixed order), so reruns are
+ * bitwise identical.  Workspace: hvms_cdf_workspace_bytes(b). */
+int64_t hvms_cdf_workspace_bytes(int64_t b);
+int hvms_cdf_backward(const float *d_params, const float *d_x, const float *d_t,
+                      float *d_grad, float *d_loss, int64_t b, void *d_ws,
+                      size_t ws_bytes, void *stream);
+
+/* One Adam step (Kingma and Ba 2015): d_m, d_v are the moment buffers,
+ * `step` counts from 1. */
+int hvms_cdf_adam_step(float *d_params, float *d_m, float *d_v, const float *d_grad,
+                       int32_t step, float lr, float beta1, float beta2, float eps,
+                       void *stream);
+
+/*
+ * Train the model on a sorted sample: d_sorted[0..m) ascending keys; the
+ * target of the i-th key is i/m.  Runs `steps` Adam steps (lr, betas 0.9 /
+ * 0.999, eps 1e-8) on minibatches of `batch` sample positions drawn with
+ * SplitMix64 from `seed`.  d_params holds the initial parameters on entry and
+ * the trained ones on exit; d_m, d_v are zeroed by the call.
+ */
+int64_t hvms_cdf_train_workspace_bytes(int64_t batch);
+int hvms_cdf_train(float *d_params, float *d_m, float *d_v, const int32_t *d_sorted,
+                   int64_t m, int64_t batch, int32_t steps, float lr, uint64_t seed,
+                   void *d_ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HVMS_H */

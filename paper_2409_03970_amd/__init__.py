@@ -1,0 +1,340 @@
+"""MI355X (gfx950) hybrid vectorized merge sort -- Python binding.
+
+Thin ctypes marshalling over libhvms.so: every function named hvms_* below
+calls the C entry point of the same name with device pointers taken from
+torch tensors and the current HIP stream; all work runs in the library's HIP
+kernels.  torch only provides device memory and streams.  Importing this
+package does not load the library; the first call does, and raises if the
+library has not been built (python -m paper_2409_03970_amd.build).
+"""
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "HvmsError", "Options", "lib", "CORANK_BINARY", "CORANK_LEARNED", "CORANK_LINEAR",
+    "CDF_PARAMS", "STAT_NAMES",
+    "hvms_sort_i32", "hvms_sort_pairs_i32", "hvms_sort_runs_i32", "hvms_merge_pass_i32",
+    "hvms_corank_i32", "hvms_segmented_sort_i32", "hvms_segmented_sort_pairs_i32",
+    "hvms_cdf_forward", "hvms_cdf_backward", "hvms_cdf_adam_step", "hvms_cdf_train",
+    "sort", "sort_pairs", "sort_runs", "merge_pass", "corank", "segmented_sort",
+    "segmented_sort_pairs", "cdf_forward", "cdf_backward", "cdf_adam_step", "cdf_train",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhvms.so")
+
+CORANK_BINARY, CORANK_LEARNED, CORANK_LINEAR = 0, 1, 2
+CDF_PARAMS = 1153
+STAT_NAMES = ("coranks", "probes", "fallbacks", "abs_err_sum", "max_err")
+
+
+class HvmsError(RuntimeError):
+    def __init__(self, fn, status):
+        msg = lib().hvms_status_string(status).decode()
+        hip = lib().hvms_last_hip_error()
+        super().__init__(f"{fn} failed: {msg} (status {status}, hip error {hip})")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    """Mirror of hvms_options (0 / None keeps a field's default)."""
+    _fields_ = [
+        ("keys_per_lane", ctypes.c_int32),
+        ("block_threads", ctypes.c_int32),
+        ("wave_levels", ctypes.c_int32),
+        ("merge_tile", ctypes.c_int32),
+        ("corank_mode", ctypes.c_int32),
+        ("radius_log2", ctypes.c_int32),
+        ("cdf_params", ctypes.c_void_p),
+        ("stats", ctypes.c_void_p),
+        ("events", ctypes.POINTER(ctypes.c_void_p)),
+        ("n_events", ctypes.c_int32),
+    ]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_sz = ctypes.c_size_t
+_f32 = ctypes.c_float
+_u64 = ctypes.c_uint64
+_opt = ctypes.POINTER(Options)
+
+_SIGS = {
+    "hvms_status_string": ([_i32], ctypes.c_char_p),
+    "hvms_last_hip_error": ([], _i32),
+    "hvms_sort_workspace_bytes": ([_i64, _i32, _opt], _i64),
+    "hvms_sort_i32": ([_vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
+    "hvms_sort_pairs_i32": ([_vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
+    "hvms_sort_runs_i32": ([_vp, _vp, _i64, _i32, _vp, _opt], _i32),
+    "hvms_merge_workspace_bytes": ([_i64, _i64, _opt], _i64),
+    "hvms_merge_pass_i32": ([_vp, _vp, _i64, _i64, _vp, _sz, _vp, _opt], _i32),
+    "hvms_corank_i32": ([_vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _opt], _i32),
+    "hvms_segmented_workspace_bytes": ([_i64, _i64, _i64, _i32, _opt], _i64),
+    "hvms_segmented_sort_i32": ([_vp, _vp, _vp, _i64, _i64, _i64, _vp, _sz, _vp, _opt], _i32),
+    "hvms_segmented_sort_pairs_i32": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _sz, _vp,
+                                       _opt], _i32),
+    "hvms_cdf_forward": ([_vp, _vp, _vp, _i64, _vp], _i32),
+    "hvms_cdf_workspace_bytes": ([_i64], _i64),
+    "hvms_cdf_backward": ([_vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp], _i32),
+    "hvms_cdf_adam_step": ([_vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _vp], _i32),
+    "hvms_cdf_train_workspace_bytes": ([_i64], _i64),
+    "hvms_cdf_train": ([_vp, _vp, _vp, _vp, _i64, _i64, _i32, _f32, _u64, _vp, _sz, _vp], _i32),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libhvms.so (raises if it was never built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2409_03970_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------------ helpers
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    return _vp(t.data_ptr())
+
+
+def _opts(opts):
+    if opts is None:
+        return None
+    if isinstance(opts, Options):
+        return ctypes.byref(opts)
+    o = Options()
+    for k, v in opts.items():
+        if k in ("cdf_params", "stats"):
+            setattr(o, k, None if v is None else v.data_ptr())
+        elif k == "events":
+            # torch.cuda.Event objects (already recorded once, so they exist)
+            arr = (ctypes.c_void_p * len(v))(*[e.cuda_event for e in v])
+            o.events = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+            o.n_events = len(v)
+            o._keep = arr
+        else:
+            setattr(o, k, int(v))
+    return ctypes.byref(o)
+
+
+def _check(fn, status):
+    if status != 0:
+        raise HvmsError(fn, status)
+
+
+def _workspace(nbytes, device):
+    if nbytes < 0:
+        raise HvmsError("workspace query", int(nbytes))
+    if nbytes == 0:
+        return None
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def _wsargs(ws):
+    if ws is None:
+        return None, 0
+    return _vp(ws.data_ptr()), ws.numel()
+
+
+# ----------------------------------------------------- C entry points (1:1)
+
+def hvms_sort_i32(d_in, d_out, ws=None, stream=None, opts=None):
+    p, b = _wsargs(ws)
+    _check("hvms_sort_i32", lib().hvms_sort_i32(
+        _ptr(d_in, torch.int32, "in"), _ptr(d_out, torch.int32, "out"), d_in.numel(), p, b,
+        _stream(stream), _opts(opts)))
+
+
+def hvms_sort_pairs_i32(k_in, v_in, k_out, v_out, ws=None, stream=None, opts=None):
+    assert k_in.numel() == v_in.numel() == k_out.numel() == v_out.numel()
+    p, b = _wsargs(ws)
+    _check("hvms_sort_pairs_i32", lib().hvms_sort_pairs_i32(
+        _ptr(k_in, torch.int32), _ptr(v_in, torch.int32), _ptr(k_out, torch.int32),
+        _ptr(v_out, torch.int32), k_in.numel(), p, b, _stream(stream), _opts(opts)))
+
+
+def hvms_sort_runs_i32(d_in, d_out, run_log2, stream=None, opts=None):
+    _check("hvms_sort_runs_i32", lib().hvms_sort_runs_i32(
+        _ptr(d_in, torch.int32), _ptr(d_out, torch.int32), d_in.numel(), int(run_log2),
+        _stream(stream), _opts(opts)))
+
+
+def hvms_merge_pass_i32(d_in, d_out, run_len, ws=None, stream=None, opts=None):
+    p, b = _wsargs(ws)
+    _check("hvms_merge_pass_i32", lib().hvms_merge_pass_i32(
+        _ptr(d_in, torch.int32), _ptr(d_out, torch.int32), d_in.numel(), int(run_len), p, b,
+        _stream(stream), _opts(opts)))
+
+
+def hvms_corank_i32(a, b, diag, out, stream=None, opts=None):
+    _check("hvms_corank_i32", lib().hvms_corank_i32(
+        _ptr(a, torch.int32), a.numel(), _ptr(b, torch.int32), b.numel(),
+        _ptr(diag, torch.int64), diag.numel(), _ptr(out, torch.int64), _stream(stream),
+        _opts(opts)))
+
+
+def hvms_segmented_sort_i32(d_in, d_out, d_offsets, n_total, max_seg, ws=None, stream=None,
+                            opts=None):
+    p, b = _wsargs(ws)
+    _check("hvms_segmented_sort_i32", lib().hvms_segmented_sort_i32(
+        _ptr(d_in, torch.int32), _ptr(d_out, torch.int32), _ptr(d_offsets, torch.int64),
+        d_offsets.numel() - 1, int(n_total), int(max_seg), p, b, _stream(stream), _opts(opts)))
+
+
+def hvms_segmented_sort_pairs_i32(k_in, v_in, k_out, v_out, d_offsets, n_total, max_seg,
+                                  ws=None, stream=None, opts=None):
+    p, b = _wsargs(ws)
+    _check("hvms_segmented_sort_pairs_i32", lib().hvms_segmented_sort_pairs_i32(
+        _ptr(k_in, torch.int32), _ptr(v_in, torch.int32), _ptr(k_out, torch.int32),
+        _ptr(v_out, torch.int32), _ptr(d_offsets, torch.int64), d_offsets.numel() - 1,
+        int(n_total), int(max_seg), p, b, _stream(stream), _opts(opts)))
+
+
+def hvms_cdf_forward(params, x, y, stream=None):
+    _check("hvms_cdf_forward", lib().hvms_cdf_forward(
+        _ptr(params, torch.float32), _ptr(x, torch.float32), _ptr(y, torch.float32), x.numel(),
+        _stream(stream)))
+
+
+def hvms_cdf_backward(params, x, t, grad, loss, ws=None, stream=None):
+    p, b = _wsargs(ws)
+    _check("hvms_cdf_backward", lib().hvms_cdf_backward(
+        _ptr(params, torch.float32), _ptr(x, torch.float32), _ptr(t, torch.float32),
+        _ptr(grad, torch.float32), _ptr(loss, torch.float32), x.numel(), p, b, _stream(stream)))
+
+
+def hvms_cdf_adam_step(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                       stream=None):
+    _check("hvms_cdf_adam_step", lib().hvms_cdf_adam_step(
+        _ptr(params, torch.float32), _ptr(m, torch.float32), _ptr(v, torch.float32),
+        _ptr(grad, torch.float32), int(step), lr, beta1, beta2, eps, _stream(stream)))
+
+
+def hvms_cdf_train(params, m, v, sorted_keys, batch, steps, lr, seed, ws=None, stream=None):
+    p, b = _wsargs(ws)
+    _check("hvms_cdf_train", lib().hvms_cdf_train(
+        _ptr(params, torch.float32), _ptr(m, torch.float32), _ptr(v, torch.float32),
+        _ptr(sorted_keys, torch.int32), sorted_keys.numel(), int(batch), int(steps), lr,
+        int(seed) & 0xFFFFFFFFFFFFFFFF, p, b, _stream(stream)))
+
+
+# -------------------------------------------------- allocating conveniences
+
+def sort(keys, out=None, opts=None, stream=None):
+    """Sorted copy of an int32 device tensor (out may be keys: in place)."""
+    if out is None:
+        out = torch.empty_like(keys)
+    ws = _workspace(lib().hvms_sort_workspace_bytes(keys.numel(), 0, _opts(opts)), keys.device)
+    hvms_sort_i32(keys, out, ws, stream, opts)
+    return out
+
+
+def sort_pairs(keys, vals, keys_out=None, vals_out=None, opts=None, stream=None):
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    vals_out = torch.empty_like(vals) if vals_out is None else vals_out
+    ws = _workspace(lib().hvms_sort_workspace_bytes(keys.numel(), 1, _opts(opts)), keys.device)
+    hvms_sort_pairs_i32(keys, vals, keys_out, vals_out, ws, stream, opts)
+    return keys_out, vals_out
+
+
+def sort_runs(keys, run_log2, out=None, opts=None, stream=None):
+    out = torch.empty_like(keys) if out is None else out
+    hvms_sort_runs_i32(keys, out, run_log2, stream, opts)
+    return out
+
+
+def merge_pass(keys, run_len, out=None, opts=None, stream=None):
+    out = torch.empty_like(keys) if out is None else out
+    ws = _workspace(lib().hvms_merge_workspace_bytes(keys.numel(), int(run_len), _opts(opts)),
+                    keys.device)
+    hvms_merge_pass_i32(keys, out, run_len, ws, stream, opts)
+    return out
+
+
+def corank(a, b, diag, opts=None, stream=None):
+    out = torch.empty(diag.numel(), dtype=torch.int64, device=a.device)
+    hvms_corank_i32(a, b, diag, out, stream, opts)
+    return out
+
+
+def segmented_sort(keys, offsets, max_seg=None, out=None, opts=None, stream=None):
+    """offsets: int64 tensor of nseg+1 entries (host or device)."""
+    out = torch.empty_like(keys) if out is None else out
+    off_host = offsets.cpu()
+    nseg = off_host.numel() - 1
+    n_total = int(off_host[-1]) if nseg >= 0 and off_host.numel() else 0
+    if max_seg is None:
+        max_seg = int((off_host[1:] - off_host[:-1]).max()) if nseg > 0 else 0
+    d_off = offsets.to(keys.device) if not offsets.is_cuda else offsets
+    ws = _workspace(lib().hvms_segmented_workspace_bytes(n_total, nseg, max_seg, 0, _opts(opts)),
+                    keys.device)
+    hvms_segmented_sort_i32(keys, out, d_off, n_total, max_seg, ws, stream, opts)
+    return out
+
+
+def segmented_sort_pairs(keys, vals, offsets, max_seg=None, opts=None, stream=None):
+    ko, vo = torch.empty_like(keys), torch.empty_like(vals)
+    off_host = offsets.cpu()
+    nseg = off_host.numel() - 1
+    n_total = int(off_host[-1]) if off_host.numel() else 0
+    if max_seg is None:
+        max_seg = int((off_host[1:] - off_host[:-1]).max()) if nseg > 0 else 0
+    d_off = offsets.to(keys.device) if not offsets.is_cuda else offsets
+    ws = _workspace(lib().hvms_segmented_workspace_bytes(n_total, nseg, max_seg, 1, _opts(opts)),
+                    keys.device)
+    hvms_segmented_sort_pairs_i32(keys, vals, ko, vo, d_off, n_total, max_seg, ws, stream, opts)
+    return ko, vo
+
+
+def cdf_forward(params, x, stream=None):
+    y = torch.empty_like(x)
+    hvms_cdf_forward(params, x, y, stream)
+    return y
+
+
+def cdf_backward(params, x, t, stream=None):
+    grad = torch.empty(CDF_PARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    ws = _workspace(lib().hvms_cdf_workspace_bytes(x.numel()), x.device)
+    hvms_cdf_backward(params, x, t, grad, loss, ws, stream)
+    return float(loss.item()), grad
+
+
+def cdf_adam_step(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                  stream=None):
+    hvms_cdf_adam_step(params, m, v, grad, step, lr, beta1, beta2, eps, stream)
+
+
+def cdf_train(params, sorted_keys, batch=65536, steps=500, lr=1e-3, seed=0, stream=None):
+    """Trains params (in place) on a sorted sample; returns (params, m, v)."""
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    ws = _workspace(lib().hvms_cdf_train_workspace_bytes(int(batch)), params.device)
+    hvms_cdf_train(params, m, v, sorted_keys, batch, steps, lr, seed, ws, stream)
+    return params, m, v

@@ -1,0 +1,288 @@
+// C ABI: argument validation, workspace layout, tuning resolution and the
+// enqueue order of the sort's kernels.  No device memory is allocated here.
+#include <stdint.h>
+#include <string.h>
+
+#include "hvms.h"
+#include "hvms_internal.h"
+
+using namespace hvms;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_status(hipError_t e)
+{
+    if (e == hipSuccess)
+        return HVMS_OK;
+    g_last_hip = (int)e;
+    return e == hipErrorInvalidValue ? HVMS_ERR_UNSUPPORTED : HVMS_ERR_HIP;
+}
+
+int ilog2_exact(int64_t x)
+{
+    int l = 0;
+    while (((int64_t)1 << l) < x)
+        ++l;
+    return l;
+}
+
+int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
+
+struct Cfg {
+    int R, NT, K, TM;
+    CorankOpts co;
+    void *const *events;
+    int n_events;
+};
+
+void trace(const Cfg &c, int idx, hipStream_t s)
+{
+    if (c.events && idx < c.n_events && c.events[idx])
+        (void)hipEventRecord((hipEvent_t)c.events[idx], s);
+}
+
+int resolve(const hvms_options *o, bool pairs, Cfg &c)
+{
+    c.R = (o && o->keys_per_lane) ? o->keys_per_lane : 16;
+    c.NT = (o && o->block_threads) ? o->block_threads : (pairs ? 512 : 512);
+    c.K = (o && o->wave_levels) ? o->wave_levels - 1 : 6;
+    c.TM = (o && o->merge_tile) ? o->merge_tile : (pairs ? 4096 : 8192);
+    if (!(o && o->merge_tile) && c.TM > 2 * c.R * c.NT)
+        c.TM = 2 * c.R * c.NT;
+    c.co.mode = o ? o->corank_mode : HVMS_CORANK_BINARY;
+    c.co.radius_log2 = (o && o->radius_log2) ? o->radius_log2 : 12;
+    c.co.cdf = o ? o->cdf_params : nullptr;
+    c.co.stats = o ? o->stats : nullptr;
+    c.events = o ? o->events : nullptr;
+    c.n_events = o ? o->n_events : 0;
+    if (c.K < 0 || c.K > 6 || c.co.radius_log2 < 0 || c.co.radius_log2 > 40)
+        return HVMS_ERR_INVALID_ARG;
+    if (c.co.mode < HVMS_CORANK_BINARY || c.co.mode > HVMS_CORANK_LINEAR)
+        return HVMS_ERR_INVALID_ARG;
+    if (c.co.mode == HVMS_CORANK_LEARNED && !c.co.cdf)
+        return HVMS_ERR_INVALID_ARG;
+    if (!block_sort_supported(c.R, c.NT, pairs) || !merge_tile_supported(c.TM, pairs))
+        return HVMS_ERR_UNSUPPORTED;
+    if ((int64_t)c.TM > 2 * (int64_t)c.R * c.NT)
+        return HVMS_ERR_UNSUPPORTED;
+    return HVMS_OK;
+}
+
+struct SortWs {
+    int64_t scratch_k, scratch_v, coranks, total;
+};
+
+SortWs sort_ws_layout(int64_t n, bool pairs, const Cfg &c)
+{
+    SortWs w{};
+    const int64_t tile = (int64_t)c.R * c.NT;
+    if (n <= tile)
+        return w;
+    w.scratch_k = 0;
+    int64_t off = align256(n * 4);
+    if (pairs) {
+        w.scratch_v = off;
+        off += align256(n * 4);
+    }
+    w.coranks = off;
+    off += align256(((n + c.TM - 1) / c.TM + 1) * 8);
+    w.total = off;
+    return w;
+}
+
+int check_ws(void *ws, size_t bytes, int64_t need)
+{
+    if (need == 0)
+        return HVMS_OK;
+    if (!ws || (int64_t)bytes < need || ((uintptr_t)ws & 255))
+        return HVMS_ERR_WORKSPACE;
+    return HVMS_OK;
+}
+
+int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
+             int64_t n, void *ws, hipStream_t s, const Cfg &c)
+{
+    const int64_t tile = (int64_t)c.R * c.NT;
+    const int lanes_log2 = ilog2_exact(c.NT);  // levels from R-runs to the tile
+    const int K = c.K;
+    const int lds_levels = lanes_log2 - K;
+    if (n <= tile)
+        return hip_status(
+            launch_block_sort(c.R, c.NT, pairs, kin, vin, kout, vout, n, K, lds_levels, false, s));
+
+    const SortWs w = sort_ws_layout(n, pairs, c);
+    char *base = (char *)ws;
+    int32_t *sk = (int32_t *)(base + w.scratch_k);
+    int32_t *sv = pairs ? (int32_t *)(base + w.scratch_v) : nullptr;
+    int64_t *cr = (int64_t *)(base + w.coranks);
+
+    const int64_t nb = (n + tile - 1) / tile;
+    const int P = ilog2_exact(nb);
+    int32_t *dk = (P % 2 == 0) ? kout : sk;
+    int32_t *dv = (P % 2 == 0) ? vout : sv;
+    trace(c, 0, s);
+    int st = hip_status(
+        launch_block_sort(c.R, c.NT, pairs, kin, vin, dk, dv, n, K, lds_levels, false, s));
+    if (st)
+        return st;
+    trace(c, 1, s);
+    int64_t run = tile;
+    for (int p = 0; p < P; ++p, run *= 2) {
+        int32_t *ok = (dk == kout) ? sk : kout;
+        int32_t *ov = (dk == kout) ? sv : vout;
+        st = hip_status(launch_pass_corank(pairs, dk, dv, n, run, c.TM, cr, c.co, s));
+        if (st)
+            return st;
+        trace(c, 2 + 2 * p, s);
+        st = hip_status(launch_merge_pass(c.TM, pairs, dk, dv, ok, ov, n, run, cr, s));
+        if (st)
+            return st;
+        trace(c, 3 + 2 * p, s);
+        dk = ok;
+        dv = ov;
+    }
+    return HVMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hvms_status_string(int status)
+{
+    switch (status) {
+    case HVMS_OK: return "ok";
+    case HVMS_ERR_INVALID_ARG: return "invalid argument";
+    case HVMS_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case HVMS_ERR_HIP: return "HIP runtime error";
+    case HVMS_ERR_UNSUPPORTED: return "unsupported tuning value";
+    default: return "unknown status";
+    }
+}
+
+int hvms_last_hip_error(void) { return g_last_hip; }
+
+int64_t hvms_sort_workspace_bytes(int64_t n, int32_t pairs, const hvms_options *opt)
+{
+    Cfg c;
+    if (n < 0)
+        return HVMS_ERR_INVALID_ARG;
+    const int st = resolve(opt, pairs != 0, c);
+    if (st)
+        return st;
+    return sort_ws_layout(n, pairs != 0, c).total;
+}
+
+int hvms_sort_i32(const int32_t *d_in, int32_t *d_out, int64_t n, void *d_ws, size_t ws_bytes,
+                  void *stream, const hvms_options *opt)
+{
+    if (n < 0 || (n > 0 && (!d_in || !d_out)))
+        return HVMS_ERR_INVALID_ARG;
+    Cfg c;
+    int st = resolve(opt, false, c);
+    if (st)
+        return st;
+    if (n == 0)
+        return HVMS_OK;
+    st = check_ws(d_ws, ws_bytes, sort_ws_layout(n, false, c).total);
+    if (st)
+        return st;
+    return run_sort(false, d_in, nullptr, d_out, nullptr, n, d_ws, (hipStream_t)stream, c);
+}
+
+int hvms_sort_pairs_i32(const int32_t *d_keys_in, const int32_t *d_vals_in, int32_t *d_keys_out,
+                        int32_t *d_vals_out, int64_t n, void *d_ws, size_t ws_bytes,
+                        void *stream, const hvms_options *opt)
+{
+    if (n < 0 || (n > 0 && (!d_keys_in || !d_vals_in || !d_keys_out || !d_vals_out)))
+        return HVMS_ERR_INVALID_ARG;
+    Cfg c;
+    int st = resolve(opt, true, c);
+    if (st)
+        return st;
+    if (n == 0)
+        return HVMS_OK;
+    st = check_ws(d_ws, ws_bytes, sort_ws_layout(n, true, c).total);
+    if (st)
+        return st;
+    return run_sort(true, d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, d_ws,
+                    (hipStream_t)stream, c);
+}
+
+int hvms_sort_runs_i32(const int32_t *d_in, int32_t *d_out, int64_t n, int32_t run_log2,
+                       void *stream, const hvms_options *opt)
+{
+    if (n < 0 || (n > 0 && (!d_in || !d_out)))
+        return HVMS_ERR_INVALID_ARG;
+    Cfg c;
+    int st = resolve(opt, false, c);
+    if (st)
+        return st;
+    const int r_log2 = ilog2_exact(c.R);
+    const int tile_log2 = r_log2 + ilog2_exact(c.NT);
+    if (run_log2 < r_log2 || run_log2 > tile_log2)
+        return HVMS_ERR_INVALID_ARG;
+    if (n == 0)
+        return HVMS_OK;
+    const int levels = run_log2 - r_log2;
+    const int K = levels < c.K ? levels : c.K;
+    const bool blocked = run_log2 < tile_log2;
+    return hip_status(launch_block_sort(c.R, c.NT, false, d_in, nullptr, d_out, nullptr, n, K,
+                                        levels - K, blocked, (hipStream_t)stream));
+}
+
+int64_t hvms_merge_workspace_bytes(int64_t n, int64_t run_len, const hvms_options *opt)
+{
+    Cfg c;
+    if (n < 0 || run_len <= 0)
+        return HVMS_ERR_INVALID_ARG;
+    const int st = resolve(opt, false, c);
+    if (st)
+        return st;
+    return align256(((n + c.TM - 1) / c.TM + 1) * 8);
+}
+
+int hvms_merge_pass_i32(const int32_t *d_in, int32_t *d_out, int64_t n, int64_t run_len,
+                        void *d_ws, size_t ws_bytes, void *stream, const hvms_options *opt)
+{
+    if (n < 0 || (n > 0 && (!d_in || !d_out)) || run_len <= 0 || (run_len & (run_len - 1)))
+        return HVMS_ERR_INVALID_ARG;
+    Cfg c;
+    int st = resolve(opt, false, c);
+    if (st)
+        return st;
+    if (2 * run_len < c.TM)
+        return HVMS_ERR_INVALID_ARG;
+    if (n == 0)
+        return HVMS_OK;
+    st = check_ws(d_ws, ws_bytes, hvms_merge_workspace_bytes(n, run_len, opt));
+    if (st)
+        return st;
+    int64_t *cr = (int64_t *)d_ws;
+    hipStream_t s = (hipStream_t)stream;
+    st = hip_status(launch_pass_corank(false, d_in, nullptr, n, run_len, c.TM, cr, c.co, s));
+    if (st)
+        return st;
+    return hip_status(launch_merge_pass(c.TM, false, d_in, nullptr, d_out, nullptr, n, run_len, cr, s));
+}
+
+int hvms_corank_i32(const int32_t *d_a, int64_t m, const int32_t *d_b, int64_t k,
+                    const int64_t *d_diag, int64_t count, int64_t *d_out, void *stream,
+                    const hvms_options *opt)
+{
+    if (m < 0 || k < 0 || count < 0 || (m > 0 && !d_a) || (k > 0 && !d_b) ||
+        (count > 0 && (!d_diag || !d_out)))
+        return HVMS_ERR_INVALID_ARG;
+    Cfg c;
+    const int st = resolve(opt, false, c);
+    if (st)
+        return st;
+    if (count == 0)
+        return HVMS_OK;
+    return hip_status(launch_corank_list(d_a, m, d_b, k, d_diag, count, d_out, c.co,
+                                         (hipStream_t)stream));
+}
+
+}  // extern "C"

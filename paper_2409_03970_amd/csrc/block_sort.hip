@@ -1,0 +1,150 @@
+// Block sort: steps a1-a4 of the sort (Sec. 2.1-2.4).
+//
+// One workgroup of NT threads sorts a tile of R * NT elements:
+//   a1  each wavefront loads 64 * R consecutive elements, lane l taking
+//       elements l, l + 64, ... (every load instruction reads 256 contiguous
+//       bytes; the column sort does not care which elements a lane holds);
+//   a2  each lane sorts its R values in VGPRs with the column network;
+//   a3  `wave_levels` cross-lane bitonic merge levels turn the 64 sorted
+//       columns into runs of R * 2^wave_levels (the transpose + row merge of
+//       the in-register sort, done in place by lane exchanges);
+//   a4  the runs go to LDS in blocked order and `lds_levels` merge-path
+//       levels merge them further, each thread producing R outputs by a
+//       serial merge from its co-rank;
+// then the tile is written back with coalesced stores.  Ragged tiles are
+// padded with the maximum of the order.
+#include "common.h"
+#include "hvms_internal.h"
+
+namespace hvms {
+
+template <int R, int NT, typename T>
+__global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restrict__ kin,
+                                                        const int32_t *__restrict__ vin,
+                                                        int32_t *__restrict__ kout,
+                                                        int32_t *__restrict__ vout, int64_t n,
+                                                        int wave_levels, int lds_levels,
+                                                        bool blocked)
+{
+    constexpr int TILE = R * NT;
+    __shared__ T S[TILE];
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int64_t tile0 = (int64_t)blockIdx.x * TILE;
+    const int64_t wave0 = tile0 + (int64_t)wave * (64 * R);
+
+    T v[R];
+    if (blocked) {
+        // Runs shorter than the tile must be consecutive input elements, so
+        // lane l needs elements R*l .. R*l+R-1 of its wave's slice: stage the
+        // tile through LDS with coalesced loads, then read it back blocked.
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int64_t g = tile0 + t + NT * j;
+            S[t + NT * j] = g < n ? load_elem<T>(kin, vin, g) : Traits<T>::kMax;
+        }
+        __syncthreads();
+        const T *W = S + wave * (64 * R) + lane * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            v[r] = W[r];
+        __syncthreads();
+    } else if (tile0 + TILE <= n) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            v[j] = load_elem<T>(kin, vin, wave0 + 64 * j + lane);
+    } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int64_t g = wave0 + 64 * j + lane;
+            v[j] = g < n ? load_elem<T>(kin, vin, g) : Traits<T>::kMax;
+        }
+    }
+
+    column_sort<R>(v);
+    wave_merge<R>(v, lane, wave_levels);
+
+    T *W = S + wave * (64 * R) + lane * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        W[r] = v[r];
+    __syncthreads();
+
+    int run = R << wave_levels;
+    for (int l = 0; l < lds_levels; ++l, run *= 2) {
+        const int o0 = t * R;
+        const int base = o0 & ~(2 * run - 1);
+        const int d = o0 - base;
+        const T *P = S + base;
+        const int i = lds_corank(P, run, run, run, d);
+        T out[R];
+        serial_merge<R>(P, run, run, run, i, d - i, out);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            S[o0 + k] = out[k];
+        __syncthreads();
+    }
+
+    if (tile0 + TILE <= n) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            store_elem<T>(kout, vout, tile0 + t + NT * j, S[t + NT * j]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int64_t g = tile0 + t + NT * j;
+            if (g < n)
+                store_elem<T>(kout, vout, g, S[t + NT * j]);
+        }
+    }
+}
+
+template <int R, int NT, typename T>
+static hipError_t launch_bs(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
+                            int64_t n, int wave_levels, int lds_levels, bool blocked,
+                            hipStream_t s)
+{
+    const int64_t tiles = (n + R * NT - 1) / (R * NT);
+    hipLaunchKernelGGL((block_sort_kernel<R, NT, T>), dim3((unsigned)tiles), dim3(NT), 0, s, kin,
+                       vin, kout, vout, n, wave_levels, lds_levels, blocked);
+    return hipGetLastError();
+}
+
+bool block_sort_supported(int R, int NT, bool pairs)
+{
+    const bool r_ok = R == 8 || R == 16 || R == 32;
+    const bool nt_ok = NT == 256 || NT == 512 || NT == 1024;
+    const long lds = (long)R * NT * (pairs ? 8 : 4);
+    return r_ok && nt_ok && lds <= 163840;
+}
+
+hipError_t launch_block_sort(int R, int NT, bool pairs, const int32_t *kin, const int32_t *vin,
+                             int32_t *kout, int32_t *vout, int64_t n, int wave_levels,
+                             int lds_levels, bool blocked, hipStream_t s)
+{
+#define HVMS_BS(RR, NN)                                                                         \
+    if (R == RR && NT == NN) {                                                                  \
+        if (pairs)                                                                              \
+            return launch_bs<RR, NN, int64_t>(kin, vin, kout, vout, n, wave_levels, lds_levels, \
+                                              blocked, s);                                               \
+        return launch_bs<RR, NN, int32_t>(kin, vin, kout, vout, n, wave_levels, lds_levels,      \
+                                          blocked, s);                                         \
+    }
+    HVMS_BS(16, 256)
+    HVMS_BS(16, 512)
+    HVMS_BS(16, 1024)
+    HVMS_BS(8, 256)
+    HVMS_BS(8, 512)
+    HVMS_BS(8, 1024)
+    HVMS_BS(32, 256)
+    HVMS_BS(32, 512)
+    if (R == 32 && NT == 1024 && !pairs)
+        return launch_bs<32, 1024, int32_t>(kin, vin, kout, vout, n, wave_levels, lds_levels,
+                                            blocked, s);
+#undef HVMS_BS
+    return hipErrorInvalidValue;
+}
+
+}  // namespace hvms

@@ -1,0 +1,262 @@
+// Device building blocks shared by the sort kernels (gfx950, wave64).
+//
+// Element types: int32_t for keys, and int64_t for (key, value) pairs packed
+// as (key << 32) | (value ^ 0x80000000), whose signed 64-bit order is the
+// lexicographic (key, value) order with both halves signed.  The pad value
+// for ragged tiles is the maximum of the order (INT32_MAX, or the pair
+// (INT32_MAX, INT32_MAX)); a real element equal to it is bit-identical, so
+// dropping the trailing pads is exact.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "networks.h"
+
+namespace hvms {
+
+template <typename T> struct Traits;
+template <> struct Traits<int32_t> {
+    static constexpr int32_t kMax = 0x7fffffff;
+};
+template <> struct Traits<int64_t> {
+    static constexpr int64_t kMax = 0x7fffffffffffffffll;
+};
+
+__device__ __forceinline__ int64_t pack_pair(int32_t k, int32_t v)
+{
+    return (int64_t)(((uint64_t)(uint32_t)k << 32) | (uint64_t)((uint32_t)v ^ 0x80000000u));
+}
+__device__ __forceinline__ int32_t pair_key(int64_t p) { return (int32_t)((uint64_t)p >> 32); }
+__device__ __forceinline__ int32_t pair_val(int64_t p)
+{
+    return (int32_t)((uint32_t)(uint64_t)p ^ 0x80000000u);
+}
+
+// Element i of a key array, or of a key/value array pair, as type T.
+template <typename T>
+__device__ __forceinline__ T load_elem(const int32_t *__restrict__ k,
+                                       const int32_t *__restrict__ v, int64_t i)
+{
+    if constexpr (sizeof(T) == 4)
+        return k[i];
+    else
+        return pack_pair(k[i], v[i]);
+}
+template <typename T>
+__device__ __forceinline__ void store_elem(int32_t *__restrict__ k, int32_t *__restrict__ v,
+                                           int64_t i, T x)
+{
+    if constexpr (sizeof(T) == 4) {
+        k[i] = x;
+    } else {
+        k[i] = pair_key(x);
+        v[i] = pair_val(x);
+    }
+}
+
+// ---------------------------------------------------------------- comparators
+
+// In-lane compare-exchange: a <- min, b <- max.  Keys: v_min_i32 + v_max_i32;
+// pairs: one 64-bit compare and four selects (the branch-free "conditional
+// select" comparator of Fig. 3b).
+template <typename T> __device__ __forceinline__ void cmpx(T &a, T &b)
+{
+    if constexpr (sizeof(T) == 4) {
+        const T lo = a < b ? a : b;
+        const T hi = a < b ? b : a;
+        a = lo;
+        b = hi;
+    } else {
+        const bool s = b < a;
+        const T lo = s ? b : a;
+        const T hi = s ? a : b;
+        a = lo;
+        b = hi;
+    }
+}
+
+// Cross-lane half of a compare-exchange: this lane keeps the min of its value
+// and its partner's (upper == false) or the max (upper == true).
+template <typename T> __device__ __forceinline__ T keep(T v, T p, bool upper)
+{
+    const bool s = p < v;
+    return (s != upper) ? p : v;
+}
+
+// ------------------------------------------------------------ lane exchange
+
+__device__ __forceinline__ int lane_id()
+{
+    return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Value of v held by lane (lane ^ M).  DPP within a 16-lane row where a
+// control exists (quad permutes, row mirrors, row rotate by 8), ds_swizzle
+// (bit-mask mode, inside 32 lanes) for xor 4, 16 and 31, and ds_bpermute for
+// the partners across the two 32-lane halves.
+template <int M> __device__ __forceinline__ int32_t xlane32(int32_t v)
+{
+    if constexpr (M == 1)
+        return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+    else if constexpr (M == 2)
+        return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+    else if constexpr (M == 3)
+        return __builtin_amdgcn_mov_dpp(v, 0x1B, 0xF, 0xF, false);  // quad_perm 3,2,1,0
+    else if constexpr (M == 4)
+        return __builtin_amdgcn_ds_swizzle(v, 0x101F);              // xor 4
+    else if constexpr (M == 7)
+        return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false); // row_half_mirror
+    else if constexpr (M == 8)
+        return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false); // row_ror:8
+    else if constexpr (M == 15)
+        return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false); // row_mirror
+    else if constexpr (M == 16)
+        return __builtin_amdgcn_ds_swizzle(v, 0x401F);              // xor 16
+    else if constexpr (M == 31)
+        return __builtin_amdgcn_ds_swizzle(v, 0x7C1F);              // xor 31
+    else
+        return __builtin_amdgcn_ds_bpermute((lane_id() ^ M) << 2, v);
+}
+
+template <int M, typename T> __device__ __forceinline__ T xlane(T v)
+{
+    if constexpr (sizeof(T) == 4) {
+        return xlane32<M>(v);
+    } else {
+        const int32_t lo = xlane32<M>((int32_t)(uint32_t)(uint64_t)v);
+        const int32_t hi = xlane32<M>((int32_t)((uint64_t)v >> 32));
+        return (T)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+    }
+}
+
+// ------------------------------------------------ per-lane column sort (a2)
+
+// Each lane sorts the R values it holds with the network table for R
+// (Sec. 2.3): 60 comparators at R = 16, Batcher's odd-even sort otherwise.
+template <int R, typename T> __device__ __forceinline__ void column_sort(T (&v)[R])
+{
+    if constexpr (R == 16) {
+#pragma unroll
+        for (int c = 0; c < HVMS_NET16_SIZE; ++c)
+            cmpx(v[HVMS_NET16[2 * c]], v[HVMS_NET16[2 * c + 1]]);
+    } else if constexpr (R == 8) {
+#pragma unroll
+        for (int c = 0; c < HVMS_NET8_SIZE; ++c)
+            cmpx(v[HVMS_NET8[2 * c]], v[HVMS_NET8[2 * c + 1]]);
+    } else if constexpr (R == 32) {
+#pragma unroll
+        for (int c = 0; c < HVMS_NET32_SIZE; ++c)
+            cmpx(v[HVMS_NET32[2 * c]], v[HVMS_NET32[2 * c + 1]]);
+    } else {
+        static_assert(R == 4, "unsupported keys per lane");
+#pragma unroll
+        for (int c = 0; c < HVMS_NET4_SIZE; ++c)
+            cmpx(v[HVMS_NET4[2 * c]], v[HVMS_NET4[2 * c + 1]]);
+    }
+}
+
+// ------------------------------------- cross-lane bitonic merge levels (a3)
+//
+// Layout: lane l holds elements R*l .. R*l + R-1 of the wavefront's tile in
+// v[0..R).  Merge level K turns sorted runs of R*2^(K-1) (2^(K-1) adjacent
+// lanes) into runs of R*2^K.  In the all-ascending form of the bitonic
+// merger, element e first meets e ^ (R*2^K - 1): lane l ^ (2^K - 1), register
+// R-1-r (the "flip").  Then half-cleaners at distances R*2^(K-2) .. R run
+// across lanes (partner lane l ^ 2^j, same register), and the ones at R/2 ..
+// 1 run inside the lane.  The in-lane part is the serial part of the hybrid
+// merger of Sec. 2.4, the cross-lane part its vectorised part.
+
+template <int R, int J, typename T>
+__device__ __forceinline__ void cross_half_cleaners(T (&v)[R], int lane)
+{
+    if constexpr (J >= 0) {
+        const bool upper = (lane >> J) & 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            v[r] = keep(v[r], xlane<(1 << J)>(v[r]), upper);
+        cross_half_cleaners<R, J - 1>(v, lane);
+    }
+}
+
+template <int R, int D, typename T> __device__ __forceinline__ void inlane_half_cleaners(T (&v)[R])
+{
+    if constexpr (D >= 1) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (!(r & D))
+                cmpx(v[r], v[r + D]);
+        inlane_half_cleaners<R, D / 2>(v);
+    }
+}
+
+template <int R, int K, typename T>
+__device__ __forceinline__ void wave_merge_level(T (&v)[R], int lane)
+{
+    constexpr int FLIP = (1 << K) - 1;
+    const bool upper = (lane >> (K - 1)) & 1;
+    T p[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        p[r] = xlane<FLIP>(v[R - 1 - r]);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        v[r] = keep(v[r], p[r], upper);
+    cross_half_cleaners<R, K - 2>(v, lane);
+    inlane_half_cleaners<R, R / 2>(v);
+}
+
+template <int R, typename T> __device__ __forceinline__ void wave_merge(T (&v)[R], int lane, int levels)
+{
+    if (levels >= 1) wave_merge_level<R, 1>(v, lane);
+    if (levels >= 2) wave_merge_level<R, 2>(v, lane);
+    if (levels >= 3) wave_merge_level<R, 3>(v, lane);
+    if (levels >= 4) wave_merge_level<R, 4>(v, lane);
+    if (levels >= 5) wave_merge_level<R, 5>(v, lane);
+    if (levels >= 6) wave_merge_level<R, 6>(v, lane);
+}
+
+// ------------------------------------------------------- merge path (a4-a6)
+
+// Co-rank of diagonal d in the merge of S[0..alen) and S[boff..boff+blen)
+// (LDS): the number of elements taken from the first run among the first d
+// outputs of the merge that takes the first run on ties.
+template <typename T>
+__device__ __forceinline__ int lds_corank(const T *S, int alen, int boff, int blen, int d)
+{
+    int lo = d > blen ? d - blen : 0;
+    int hi = d < alen ? d : alen;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (S[boff + d - 1 - mid] < S[mid])
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Serial merge of VT outputs starting at positions (i, j) of the two runs in
+// S (first run at 0, second at boff); one LDS read per output.
+template <int VT, typename T>
+__device__ __forceinline__ void serial_merge(const T *S, int alen, int boff, int blen, int i, int j,
+                                             T (&out)[VT])
+{
+    T a = S[i < alen ? i : (alen > 0 ? alen - 1 : 0)];
+    T b = S[boff + (j < blen ? j : (blen > 0 ? blen - 1 : 0))];
+#pragma unroll
+    for (int k = 0; k < VT; ++k) {
+        const bool takeB = (j < blen) && (i >= alen || b < a);
+        out[k] = takeB ? b : a;
+        i += takeB ? 0 : 1;
+        j += takeB ? 1 : 0;
+        int ia = i < alen ? i : alen - 1;
+        int ib = j < blen ? j : blen - 1;
+        int addr = takeB ? boff + (ib < 0 ? 0 : ib) : (ia < 0 ? 0 : ia);
+        const T nx = S[addr];
+        a = takeB ? a : nx;
+        b = takeB ? nx : b;
+    }
+}
+
+}  // namespace hvms

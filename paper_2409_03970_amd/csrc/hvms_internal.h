@@ -1,0 +1,34 @@
+// Internal launcher interface between the C ABI (abi.hip) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hvms {
+
+struct CorankOpts {
+    int mode;
+    int radius_log2;
+    const float *cdf;
+    unsigned long long *stats;
+};
+
+// block_sort.hip
+bool block_sort_supported(int R, int NT, bool pairs);
+hipError_t launch_block_sort(int R, int NT, bool pairs, const int32_t *kin, const int32_t *vin,
+                             int32_t *kout, int32_t *vout, int64_t n, int wave_levels,
+                             int lds_levels, bool blocked, hipStream_t s);
+
+// merge.hip
+bool merge_tile_supported(int tm, bool pairs);
+hipError_t launch_pass_corank(bool pairs, const int32_t *kin, const int32_t *vin, int64_t n,
+                              int64_t run, int64_t tm, int64_t *cr, const CorankOpts &o,
+                              hipStream_t s);
+hipError_t launch_merge_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
+                             int32_t *kout, int32_t *vout, int64_t n, int64_t run,
+                             const int64_t *cr, hipStream_t s);
+hipError_t launch_corank_list(const int32_t *a, int64_t m, const int32_t *b, int64_t k,
+                              const int64_t *diag, int64_t count, int64_t *out,
+                              const CorankOpts &o, hipStream_t s);
+
+}  // namespace hvms

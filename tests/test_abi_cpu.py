@@ -1,0 +1,95 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol,
+and rejects bad arguments on the host before enqueueing anything."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2409_03970_amd as hv
+import sys
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hvms.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(hv.LIB_PATH), reason="libhvms.so not built")
+
+FAKE = ctypes.c_void_p(0x100000)       # never dereferenced: every call below fails validation
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(hvms_[a-z_0-9]+)\s*\(",
+                                 text, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) == 18
+    L = hv.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(hv._SIGS), set(names) ^ set(hv._SIGS)
+
+
+def test_python_names_match_c_names():
+    for n in _declared():
+        if n in ("hvms_status_string", "hvms_last_hip_error") or n.endswith("_workspace_bytes"):
+            continue
+        assert callable(getattr(hv, n)), n
+
+
+def test_status_strings():
+    L = hv.lib()
+    assert L.hvms_status_string(0) == b"ok"
+    for s in (-1, -2, -3, -4):
+        assert L.hvms_status_string(s) != b"unknown status"
+
+
+def test_workspace_queries():
+    L = hv.lib()
+    assert L.hvms_sort_workspace_bytes(0, 0, None) == 0
+    assert L.hvms_sort_workspace_bytes(100, 0, None) == 0          # one tile needs none
+    a = L.hvms_sort_workspace_bytes(1 << 20, 0, None)
+    b = L.hvms_sort_workspace_bytes(1 << 21, 0, None)
+    c = L.hvms_sort_workspace_bytes(1 << 20, 1, None)
+    assert 4 * (1 << 20) <= a < b and c >= 8 * (1 << 20)
+    assert a % 256 == 0 and c % 256 == 0
+    assert L.hvms_sort_workspace_bytes(-1, 0, None) == -1
+    o = hv.Options(keys_per_lane=7)
+    assert L.hvms_sort_workspace_bytes(1000, 0, ctypes.byref(o)) == -4
+    assert L.hvms_merge_workspace_bytes(1 << 20, 4096, None) > 0
+
+
+def test_argument_errors_before_any_launch():
+    L = hv.lib()
+    assert L.hvms_sort_i32(None, None, -1, None, 0, None, None) == -1
+    assert L.hvms_sort_i32(None, FAKE, 5, None, 0, None, None) == -1
+    assert L.hvms_sort_i32(FAKE, FAKE, 0, None, 0, None, None) == 0          # n = 0: no-op
+    # a multi-tile sort without workspace, with a short one, with a misaligned one
+    assert L.hvms_sort_i32(FAKE, FAKE, 1 << 20, None, 0, None, None) == -2
+    assert L.hvms_sort_i32(FAKE, FAKE, 1 << 20, FAKE, 16, None, None) == -2
+    assert L.hvms_sort_i32(FAKE, FAKE, 1 << 20, ctypes.c_void_p(0x100004), 1 << 30, None, None) == -2
+    bad = hv.Options(block_threads=300)
+    assert L.hvms_sort_i32(FAKE, FAKE, 10, None, 0, None, ctypes.byref(bad)) == -4
+    learned_without_model = hv.Options(corank_mode=1)
+    assert L.hvms_sort_i32(FAKE, FAKE, 10, None, 0, None, ctypes.byref(learned_without_model)) == -1
+    assert L.hvms_sort_pairs_i32(FAKE, None, FAKE, FAKE, 3, None, 0, None, None) == -1
+    assert L.hvms_sort_runs_i32(FAKE, FAKE, 100, 2, None, None) == -1        # run below R
+    assert L.hvms_sort_runs_i32(FAKE, FAKE, 100, 20, None, None) == -1       # run above tile
+    assert L.hvms_merge_pass_i32(FAKE, FAKE, 100, 3000, None, 0, None, None) == -1  # not 2^k
+    assert L.hvms_corank_i32(None, 5, FAKE, 5, FAKE, 1, FAKE, None, None) == -1
+    assert L.hvms_corank_i32(FAKE, 5, FAKE, 5, FAKE, 0, FAKE, None, None) == 0
+
+
+def test_every_option_set_of_the_gpu_tests_is_accepted():
+    import test_gpu_sort as g
+    L = hv.lib()
+    sets = list(g.TUNINGS) + [dict(keys_per_lane=R, block_threads=NT)
+                              for R in (8, 16, 32) for NT in (256, 512, 1024)
+                              if not (R == 32 and NT == 1024)]
+    for o in sets:
+        assert L.hvms_sort_workspace_bytes(1 << 20, 0, hv._opts(o)) >= 0, o
+        assert L.hvms_sort_runs_i32(FAKE, FAKE, 0, 4 if o["keys_per_lane"] <= 16 else 5,
+                                    None, hv._opts(o)) == 0, o

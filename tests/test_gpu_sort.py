@@ -1,0 +1,260 @@
+"""GPU parity of the sort path against the CPU oracle (bit-exact), through the
+C ABI.  Networks are checked on every 0-1 input (0-1 principle)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2409_03970_amd as hv
+from paper_2409_03970_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------- 0-1 principle on the GPU
+
+def _runs_from_bits(X, R):
+    """All 2^X 0-1 inputs of X keys, one run each (X <= 16)."""
+    q = torch.arange(1 << X, device=DEV, dtype=torch.int64)
+    bits = (q[:, None] >> torch.arange(X, device=DEV)) & 1
+    return bits.to(torch.int32).reshape(-1)
+
+
+@pytest.mark.parametrize("R", [8, 16])
+def test_column_network_all_01_inputs(R):
+    # runs of R keys = the per-lane network alone; every run must come out sorted
+    _say("column network 0-1, R =", R)
+    x = _runs_from_bits(R, R)
+    y = hv.sort_runs(x, int(np.log2(R)), opts={"keys_per_lane": R, "block_threads": 256})
+    torch.cuda.synchronize()
+    runs = y.view(-1, R)
+    ones = x.view(-1, R).sum(1)
+    want = (torch.arange(R, device=DEV)[None, :] >= (R - ones)[:, None]).to(torch.int32)
+    assert torch.equal(runs, want)
+
+
+def test_column_network_32_random_01_inputs():
+    g = torch.Generator(device=DEV)
+    g.manual_seed(5)
+    x = torch.randint(0, 2, (1 << 22,), generator=g, device=DEV, dtype=torch.int32)
+    y = hv.sort_runs(x, 5, opts={"keys_per_lane": 32, "block_threads": 256})
+    ones = x.view(-1, 32).sum(1)
+    want = (torch.arange(32, device=DEV)[None, :] >= (32 - ones)[:, None]).to(torch.int32)
+    assert torch.equal(y.view(-1, 32), want)
+
+
+def _sorted_halves(X, device=DEV):
+    """All (X/2 + 1)^2 0-1 runs of X keys whose halves are each sorted."""
+    h = X // 2
+    z1 = torch.arange(h + 1, device=device).repeat_interleave(h + 1)
+    z2 = torch.arange(h + 1, device=device).repeat(h + 1)
+    pos = torch.arange(h, device=device)[None, :]
+    first = (pos >= z1[:, None]).to(torch.int32)
+    second = (pos >= z2[:, None]).to(torch.int32)
+    return torch.cat([first, second], 1).reshape(-1), z1 + z2
+
+
+@pytest.mark.parametrize("R", [8, 16])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_wave_merge_level_all_sorted_halves(R, k):
+    # runs of X = R * 2^k: the levels below k keep the sorted halves as they
+    # are, so level k sees every sorted-halves 0-1 input
+    X = R << k
+    _say("wave merge level", k, "R", R, "X", X)
+    x, zeros = _sorted_halves(X)
+    y = hv.sort_runs(x, int(np.log2(X)), opts={"keys_per_lane": R, "block_threads": 256})
+    want = (torch.arange(X, device=DEV)[None, :] >= zeros[:, None]).to(torch.int32)
+    assert torch.equal(y.view(-1, X), want)
+
+
+@pytest.mark.parametrize("X", [2048, 4096, 8192])
+def test_lds_merge_levels_sorted_halves(X):
+    # LDS merge-path levels (not a network): a strided subset of the
+    # sorted-halves inputs plus all extreme splits
+    h = X // 2
+    zs = sorted(set(list(range(0, h + 1, 97)) + [0, 1, 2, h - 2, h - 1, h]))
+    z = torch.tensor(zs, device=DEV)
+    z1 = z.repeat_interleave(len(zs))
+    z2 = z.repeat(len(zs))
+    pos = torch.arange(h, device=DEV)[None, :]
+    x = torch.cat([(pos >= z1[:, None]), (pos >= z2[:, None])], 1).to(torch.int32).reshape(-1)
+    y = hv.sort_runs(x, int(np.log2(X)), opts={"block_threads": 512})
+    want = (torch.arange(X, device=DEV)[None, :] >= (z1 + z2)[:, None]).to(torch.int32)
+    assert torch.equal(y.view(-1, X), want)
+
+
+# ------------------------------------------------------ runs vs the oracle
+
+@pytest.mark.parametrize("R,NT", [(16, 256), (16, 512), (8, 256), (32, 256), (16, 1024)])
+def test_sort_runs_match_oracle(R, NT):
+    n = 3 * R * NT + 77
+    x = inputs.keys(n, "uniform", seed=R + NT, device=DEV)
+    xs = x.cpu().numpy()
+    for run_log2 in range(int(np.log2(R)), int(np.log2(R * NT)) + 1):
+        _say("sort_runs", R, NT, run_log2)
+        y = hv.sort_runs(x, run_log2, opts={"keys_per_lane": R, "block_threads": NT}).cpu().numpy()
+        X = 1 << run_log2
+        offs = np.append(np.arange(0, n, X), n)
+        assert np.array_equal(y, oracle.segmented_sort(xs, offs))
+
+
+# ----------------------------------------------------------- full sort
+
+SIZES = [1, 2, 3, 15, 16, 17, 63, 64, 65, 100, 1023, 1024, 1025, 4095, 4096, 4097, 8191, 8192,
+         8193, 12289, 65535, 65536, 65537, 100003, (1 << 20) + 3]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_sort_matches_oracle_sizes(n):
+    _say("sort n =", n)
+    x = inputs.keys(n, "uniform", seed=n, device=DEV)
+    y = hv.sort(x)
+    assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy()))
+
+
+@pytest.mark.parametrize("dist", list(inputs.DISTRIBUTIONS) + ["mixture"])
+@pytest.mark.parametrize("n", [777777, 1 << 21])
+def test_sort_matches_oracle_distributions(dist, n):
+    _say("sort", dist, n)
+    x = inputs.keys(n, dist, seed=11, device=DEV)
+    y = hv.sort(x)
+    assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy()))
+
+
+@pytest.mark.parametrize("pattern", ["equal", "two_values", "extremes", "organ_pipe", "sawtooth",
+                                     "negatives"])
+def test_sort_adversarial(pattern):
+    for n in (5, 4097, 300001):
+        x = inputs.adversarial_keys(n, pattern, seed=2, device=DEV)
+        y = hv.sort(x)
+        assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy())), (pattern, n)
+
+
+def test_sort_in_place_and_input_untouched():
+    x = inputs.keys(300007, "uniform", seed=3, device=DEV)
+    ref = oracle.sort(x.cpu().numpy())
+    keep = x.clone()
+    y = hv.sort(x)
+    assert torch.equal(x, keep)
+    hv.sort(x, out=x)
+    assert np.array_equal(x.cpu().numpy(), ref) and np.array_equal(y.cpu().numpy(), ref)
+
+
+TUNINGS = [
+    dict(keys_per_lane=R, block_threads=NT, merge_tile=TM, wave_levels=K + 1)
+    for (R, NT) in [(8, 256), (8, 1024), (16, 256), (16, 512), (16, 1024), (32, 256), (32, 512),
+                    (32, 1024)]
+    for TM in (2048, 4096, 8192, 16384) if TM <= 2 * R * NT
+    for K in (6, 3, 0)
+]
+
+
+@pytest.mark.parametrize("opt", TUNINGS, ids=lambda o: "R{keys_per_lane}_NT{block_threads}_TM{merge_tile}_K{wave_levels}".format(**o))
+def test_sort_every_tuning(opt):
+    n = 5 * opt["keys_per_lane"] * opt["block_threads"] + 12345
+    x = inputs.keys(n, "zipf", seed=7, device=DEV)
+    y = hv.sort(x, opts=opt)
+    assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy()))
+
+
+def test_sort_on_a_side_stream():
+    s = torch.cuda.Stream()
+    x = inputs.keys(1 << 20, "uniform", seed=9, device=DEV)
+    with torch.cuda.stream(s):
+        y = hv.sort(x)
+    s.synchronize()
+    assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy()))
+
+
+# ------------------------------------------------------------- pairs
+
+@pytest.mark.parametrize("n", [1, 17, 4097, 65537, 1000003])
+@pytest.mark.parametrize("dist", ["uniform", "distinct16", "zipf", "reverse"])
+def test_sort_pairs_match_oracle(n, dist):
+    _say("pairs", n, dist)
+    k = inputs.keys(n, dist, seed=n, device=DEV)
+    v = torch.randint(-3, 3, (n,), device=DEV, dtype=torch.int32)
+    ko, vo = hv.sort_pairs(k, v)
+    ek, ev = oracle.sort_pairs(k.cpu().numpy(), v.cpu().numpy())
+    assert np.array_equal(ko.cpu().numpy(), ek) and np.array_equal(vo.cpu().numpy(), ev)
+
+
+@pytest.mark.parametrize("opt", [dict(keys_per_lane=R, block_threads=NT, merge_tile=TM)
+                                 for R, NT in [(16, 256), (16, 512), (8, 1024), (32, 256), (16, 1024)]
+                                 for TM in (2048, 4096, 8192) if TM <= 2 * R * NT])
+def test_sort_pairs_every_tuning(opt):
+    n = 3 * opt["keys_per_lane"] * opt["block_threads"] + 999
+    k, v = inputs.pairs(n, "distinct16", seed=1, device=DEV)
+    ko, vo = hv.sort_pairs(k, v, opts=opt)
+    ek, ev = oracle.sort_pairs(k.cpu().numpy(), v.cpu().numpy())
+    assert np.array_equal(ko.cpu().numpy(), ek) and np.array_equal(vo.cpu().numpy(), ev)
+
+
+# ------------------------------------------------- merge pass and co-rank
+
+@pytest.mark.parametrize("run", [4096, 8192, 65536])
+@pytest.mark.parametrize("n_runs", [1, 2, 3, 7])
+def test_merge_pass_matches_oracle(run, n_runs):
+    n = run * n_runs - (run // 3 if n_runs > 1 else 0)
+    x = inputs.keys(n, "distinct16", seed=run + n_runs, device=DEV).cpu().numpy()
+    offs = np.append(np.arange(0, n, run), n)
+    runs = oracle.segmented_sort(x, offs)
+    y = hv.merge_pass(torch.from_numpy(runs).to(DEV), run).cpu().numpy()
+    want = np.concatenate([oracle.merge(runs[a:min(a + run, n)], runs[min(a + run, n):min(a + 2 * run, n)])
+                           for a in range(0, n, 2 * run)])
+    assert np.array_equal(y, want)
+
+
+@pytest.mark.parametrize("mode", [hv.CORANK_BINARY, hv.CORANK_LINEAR])
+@pytest.mark.parametrize("seed", range(6))
+def test_corank_all_diagonals_match_oracle(mode, seed):
+    rng = np.random.default_rng(seed)
+    m, k = int(rng.integers(0, 3000)), int(rng.integers(0, 3000))
+    hi = int(rng.integers(1, 50))
+    A = np.sort(rng.integers(0, hi, m)).astype(np.int32)
+    B = np.sort(rng.integers(0, hi, k)).astype(np.int32)
+    diag = np.arange(-1, m + k + 2, dtype=np.int64)
+    got = hv.corank(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV),
+                    torch.from_numpy(diag).to(DEV), opts={"corank_mode": mode, "radius_log2": 3}).cpu().numpy()
+    want = [oracle.corank(A, B, int(d)) for d in diag]
+    assert got.tolist() == want
+
+
+def test_corank_stats_count_probes():
+    A = torch.arange(0, 2000000, 2, device=DEV, dtype=torch.int32)
+    B = torch.arange(1, 2000000, 2, device=DEV, dtype=torch.int32)
+    diag = torch.arange(1, 2000000, 1001, device=DEV, dtype=torch.int64)
+    st = torch.zeros(8, dtype=torch.int64, device=DEV)
+    got = hv.corank(A, B, diag, opts={"corank_mode": hv.CORANK_LINEAR, "radius_log2": 4, "stats": st})
+    assert torch.equal(got, (diag + 1) // 2)
+    s = st.cpu().tolist()
+    assert s[0] == diag.numel() and s[2] == 0          # interleaved runs: prediction exact
+    assert s[1] <= diag.numel() * 7                     # bracket check + log2(2 * 16) + 1
+
+
+# ------------------------------------------------------- full-size check
+
+def _full_check(x, y):
+    xs, ys = x.cpu().numpy(), y.cpu().numpy()
+    assert np.all(ys[1:] >= ys[:-1])
+    assert oracle.multiset_hash(ys) == oracle.multiset_hash(xs)
+    n = xs.size
+    for p in [0, 1, n // 3, n // 2, n - 2, n - 1]:
+        lt, le = oracle.count(xs, ys[p])
+        assert lt <= p < le, p
+
+
+@pytest.mark.parametrize("dist", inputs.DISTRIBUTIONS)
+def test_full_size_2pow28(dist):
+    # the benchmark's workload and launch configuration: 2^28 keys
+    n = 1 << 28
+    _say("full size", dist)
+    x = inputs.keys(n, dist, seed=0, device=DEV)
+    y = hv.sort(x)
+    torch.cuda.synchronize()
+    _full_check(x, y)
