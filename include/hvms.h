@@ -68,6 +68,10 @@ enum {
  *                   binary search when the co-rank lies outside (default 12).
  *   stats           optional device array of HVMS_STATS_WORDS uint64 counters
  *                   the co-rank kernels add to (see HVMS_STAT_*), or NULL.
+ *   merge_variant   global merge kernel: 0 default, 1 one tile per workgroup,
+ *                   2 persistent with the next tile prefetched during the
+ *                   merge, 3 as 2 with each XCD walking contiguous tiles.
+ *   merge_occupancy workgroups per CU in the persistent grid (0 = all that fit).
  *   events/n_events optional caller-owned hipEvent_t handles for tracing: a
  *                   sort records events[0]/[1] around its block-sort kernel
  *                   and events[2+2p]/[3+2p] around the merge kernel of pass p
@@ -84,6 +88,8 @@ typedef struct hvms_options {
     unsigned long long *stats;
     void *const *events;
     int32_t n_events;
+    int32_t merge_variant;
+    int32_t merge_occupancy;
 } hvms_options;
 
 enum {

@@ -51,6 +51,8 @@ class Options(ctypes.Structure):
         ("stats", ctypes.c_void_p),
         ("events", ctypes.POINTER(ctypes.c_void_p)),
         ("n_events", ctypes.c_int32),
+        ("merge_variant", ctypes.c_int32),
+        ("merge_occupancy", ctypes.c_int32),
     ]
 
 

@@ -31,7 +31,7 @@ int ilog2_exact(int64_t x)
 int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
 struct Cfg {
-    int R, NT, K, TM;
+    int R, NT, K, TM, variant, occupancy;
     CorankOpts co;
     void *const *events;
     int n_events;
@@ -51,6 +51,10 @@ int resolve(const hvms_options *o, bool pairs, Cfg &c)
     c.TM = (o && o->merge_tile) ? o->merge_tile : (pairs ? 4096 : 8192);
     if (!(o && o->merge_tile) && c.TM > 2 * c.R * c.NT)
         c.TM = 2 * c.R * c.NT;
+    c.variant = o ? o->merge_variant : 0;
+    c.occupancy = o ? o->merge_occupancy : 0;
+    if (c.variant < 0 || c.variant > 3 || c.occupancy < 0 || c.occupancy > 32)
+        return HVMS_ERR_INVALID_ARG;
     c.co.mode = o ? o->corank_mode : HVMS_CORANK_BINARY;
     c.co.radius_log2 = (o && o->radius_log2) ? o->radius_log2 : 12;
     c.co.cdf = o ? o->cdf_params : nullptr;
@@ -136,7 +140,8 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
         if (st)
             return st;
         trace(c, 2 + 2 * p, s);
-        st = hip_status(launch_merge_pass(c.TM, pairs, dk, dv, ok, ov, n, run, cr, s));
+        st = hip_status(launch_merge_pass(c.TM, pairs, dk, dv, ok, ov, n, run, cr, c.variant,
+                                          c.occupancy, s));
         if (st)
             return st;
         trace(c, 3 + 2 * p, s);
@@ -265,7 +270,8 @@ int hvms_merge_pass_i32(const int32_t *d_in, int32_t *d_out, int64_t n, int64_t 
     st = hip_status(launch_pass_corank(false, d_in, nullptr, n, run_len, c.TM, cr, c.co, s));
     if (st)
         return st;
-    return hip_status(launch_merge_pass(c.TM, false, d_in, nullptr, d_out, nullptr, n, run_len, cr, s));
+    return hip_status(launch_merge_pass(c.TM, false, d_in, nullptr, d_out, nullptr, n, run_len,
+                                       cr, c.variant, c.occupancy, s));
 }
 
 int hvms_corank_i32(const int32_t *d_a, int64_t m, const int32_t *d_b, int64_t k,

@@ -24,9 +24,13 @@ bool merge_tile_supported(int tm, bool pairs);
 hipError_t launch_pass_corank(bool pairs, const int32_t *kin, const int32_t *vin, int64_t n,
                               int64_t run, int64_t tm, int64_t *cr, const CorankOpts &o,
                               hipStream_t s);
+// variant: 0 default (= 2), 1 one tile per workgroup, 2 persistent pipelined,
+// 3 persistent pipelined with XCD-grouped tiles; occupancy: workgroups per CU
+// of the persistent grid (0 = as many as fit).
 hipError_t launch_merge_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
                              int32_t *kout, int32_t *vout, int64_t n, int64_t run,
-                             const int64_t *cr, hipStream_t s);
+                             const int64_t *cr, int variant, int occupancy, hipStream_t s);
+int device_cus();
 hipError_t launch_corank_list(const int32_t *a, int64_t m, const int32_t *b, int64_t k,
                               const int64_t *diag, int64_t count, int64_t *out,
                               const CorankOpts &o, hipStream_t s);

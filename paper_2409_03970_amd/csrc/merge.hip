@@ -274,6 +274,251 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(const int32_t *__restric
     }
 }
 
+// ------------------------------------------- persistent, pipelined merge pass
+//
+// Same tiles and co-ranks as merge_pass_kernel, but each workgroup walks a
+// sequence of tiles and overlaps HBM with LDS work: while tile g is merged
+// out of LDS, the A and B windows of its next tile are already in flight
+// into registers (16-byte loads of the 4-element chunks that cover each
+// window), and the co-ranks of the tile after that are loaded too.  Barriers
+// fence LDS only, so the prefetch stays in flight across them.
+
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+struct TileGeo {
+    int64_t o0;     // first output index of the tile
+    int64_t a_al;   // A window start, rounded down to a 4-element chunk
+    int64_t b_al;   // B window start, rounded down
+    int cnt;        // outputs in the tile
+    int acnt, bcnt; // window lengths
+    int a_off;      // A window start - a_al
+    int nA, nB;     // chunks covering the A and B windows
+    int b_base;     // LDS index of B element 0
+};
+
+__device__ __forceinline__ TileGeo tile_geo(int64_t g, int64_t tm, int64_t n, int64_t run,
+                                            int64_t c0, int64_t c1)
+{
+    TileGeo G;
+    const int64_t o0 = g * tm;
+    const int64_t o1 = o0 + tm < n ? o0 + tm : n;
+    const int64_t pb = o0 & ~(2 * run - 1);
+    const int64_t alen = run < n - pb ? run : n - pb;
+    const int64_t rest = n - pb - run;
+    const int64_t blen = rest <= 0 ? 0 : (rest < run ? rest : run);
+    const int64_t d0 = o0 - pb, d1 = o1 - pb;
+    auto clampc = [&](int64_t i, int64_t d) {
+        const int64_t lo = d > blen ? d - blen : 0, hi = d < alen ? d : alen;
+        return i < lo ? lo : (i > hi ? hi : i);
+    };
+    const int64_t i0 = clampc(c0, d0);
+    int64_t i1 = clampc(d1 == alen + blen ? alen : c1, d1);
+    i1 = i1 < i0 ? i0 : (i1 > i0 + (d1 - d0) ? i0 + (d1 - d0) : i1);
+    G.o0 = o0;
+    G.cnt = (int)(d1 - d0);
+    G.acnt = (int)(i1 - i0);
+    G.bcnt = G.cnt - G.acnt;
+    const int64_t abeg = pb + i0, bbeg = pb + run + (d0 - i0);
+    G.a_al = abeg & ~(int64_t)3;
+    G.b_al = bbeg & ~(int64_t)3;
+    G.a_off = (int)(abeg - G.a_al);
+    const int b_off = (int)(bbeg - G.b_al);
+    G.nA = G.acnt ? (G.a_off + G.acnt + 3) >> 2 : 0;
+    G.nB = G.bcnt ? (b_off + G.bcnt + 3) >> 2 : 0;
+    G.b_base = 4 * G.nA + b_off;
+    return G;
+}
+
+template <typename T> struct Chunk;
+template <> struct Chunk<int32_t> {
+    int4 k;
+};
+template <> struct Chunk<int64_t> {
+    int4 k, v;
+};
+
+// Chunk of the 4 elements starting at e (e % 4 == 0) with one 16-byte load
+// per array.  The caller keeps e + 4 <= n; the single ragged chunk at the end
+// of an array whose length is not a multiple of 4 is patched by fix_tail.
+template <typename T>
+__device__ __forceinline__ Chunk<T> load_chunk(const int32_t *__restrict__ k,
+                                               const int32_t *__restrict__ v, int64_t e)
+{
+    Chunk<T> c;
+    c.k = *(const int4 *)(k + e);
+    if constexpr (sizeof(T) == 8)
+        c.v = *(const int4 *)(v + e);
+    return c;
+}
+
+template <typename T>
+__device__ __forceinline__ void fix_tail(Chunk<T> &c, const int32_t *__restrict__ k,
+                                         const int32_t *__restrict__ v, int64_t e, int64_t n)
+{
+    int kk[4], vv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        kk[q] = e + q < n ? k[e + q] : 0x7fffffff;
+        if constexpr (sizeof(T) == 8)
+            vv[q] = e + q < n ? v[e + q] : 0x7fffffff;
+    }
+    c.k = make_int4(kk[0], kk[1], kk[2], kk[3]);
+    if constexpr (sizeof(T) == 8)
+        c.v = make_int4(vv[0], vv[1], vv[2], vv[3]);
+}
+
+template <typename T> __device__ __forceinline__ void put_chunk(T *S, int c, const Chunk<T> &x)
+{
+    if constexpr (sizeof(T) == 4) {
+        *(int4 *)(S + 4 * c) = x.k;
+    } else {
+        S[4 * c + 0] = pack_pair(x.k.x, x.v.x);
+        S[4 * c + 1] = pack_pair(x.k.y, x.v.y);
+        S[4 * c + 2] = pack_pair(x.k.z, x.v.z);
+        S[4 * c + 3] = pack_pair(x.k.w, x.v.w);
+    }
+}
+
+template <int NT, int VT, typename T>
+__global__ __launch_bounds__(NT) void merge_pass_pipe_kernel(
+    const int32_t *__restrict__ kin, const int32_t *__restrict__ vin, int32_t *__restrict__ kout,
+    int32_t *__restrict__ vout, int64_t n, int64_t run, const int64_t *__restrict__ cr,
+    int64_t ntiles, int xcd_group)
+{
+    constexpr int TM = NT * VT;
+    constexpr int CH = VT / 4 + 1;  // chunk slots per thread: TM/4 + 2 chunks at most
+    __shared__ __attribute__((aligned(16))) T S[TM + 16];
+    const int t = threadIdx.x;
+
+    // Tile order: plain round robin over workgroups, or (xcd_group) the
+    // workgroups of one XCD (blockIdx % 8 when dispatch is round robin over
+    // 8 XCDs) walk one contiguous eighth of the tiles, so neighbouring tiles
+    // share window-boundary cache lines in that XCD's L2.
+    int64_t first, step, last;
+    if (xcd_group) {
+        const int64_t nx = 8, x = blockIdx.x % nx, slot = blockIdx.x / nx;
+        const int64_t slots = gridDim.x / nx;
+        const int64_t per = (ntiles + nx - 1) / nx;
+        first = x * per + slot;
+        step = slots;
+        last = (x + 1) * per < ntiles ? (x + 1) * per : ntiles;
+    } else {
+        first = blockIdx.x;
+        step = gridDim.x;
+        last = ntiles;
+    }
+    if (first >= last)
+        return;
+
+    // co-ranks of a tile, as vector loads (lanes 0 and 1) so that waiting for
+    // them never waits for LDS traffic
+    auto load_cr = [&](int64_t g) -> int64_t {
+        const int64_t idx = g + (t & 1);
+        return cr[idx < ntiles ? idx : ntiles - 1];
+    };
+    auto geo_of = [&](int64_t g, int64_t crv) {
+        const int64_t c0 = __builtin_amdgcn_readlane((int)(uint32_t)crv, 0) |
+                           ((int64_t)__builtin_amdgcn_readlane((int)(crv >> 32), 0) << 32);
+        const int64_t c1 = __builtin_amdgcn_readlane((int)(uint32_t)crv, 1) |
+                           ((int64_t)__builtin_amdgcn_readlane((int)(crv >> 32), 1) << 32);
+        return tile_geo(g, TM, n, run, c0, c1);
+    };
+    // Chunk c of a tile: A chunks first, then B chunks.  Slots are guarded
+    // per wavefront (uniform branch) and every lane loads from an in-bounds
+    // address, so no two loads ever write the same registers on different
+    // paths and the prefetch stays in flight.
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int64_t e_tail = n & ~(int64_t)3;   // start of the ragged chunk
+    const bool has_tail = (n & 3) != 0;
+    auto chunk_elem = [&](const TileGeo &G, int c) -> int64_t {
+        return c < G.nA ? G.a_al + 4 * c : G.b_al + 4 * (c - G.nA);
+    };
+    Chunk<T> pf[CH];
+    auto prefetch = [&](const TileGeo &G) {
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            if (NT * q + 64 * wave < G.nA + G.nB) {
+                const int c = t + NT * q;
+                int64_t e = c < G.nA + G.nB ? chunk_elem(G, c) : 0;
+                e = (has_tail && e == e_tail) ? e_tail - 4 : e;
+                pf[q] = load_chunk<T>(kin, vin, e);
+            }
+        }
+    };
+    int64_t g = first;
+    TileGeo cur = geo_of(g, load_cr(g));
+    prefetch(cur);
+    int64_t crn = g + step < last ? load_cr(g + step) : 0;
+
+    for (;;) {
+        lds_barrier();  // the previous tile's store has read S
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int c = t + NT * q;
+            if (c < cur.nA + cur.nB) {
+                if (has_tail && chunk_elem(cur, c) == e_tail)
+                    fix_tail<T>(pf[q], kin, vin, e_tail, n);
+                put_chunk<T>(S, c, pf[q]);
+            }
+        }
+        lds_barrier();
+
+        const int64_t gn = g + step;
+        const bool more = gn < last;
+        TileGeo nxt;
+        if (more) {
+            nxt = geo_of(gn, crn);
+            prefetch(nxt);
+            crn = gn + step < last ? load_cr(gn + step) : 0;
+        }
+
+        const T *A = S + cur.a_off;
+        const int boff = cur.b_base - cur.a_off;
+        const int diag = t * VT < cur.cnt ? t * VT : cur.cnt;
+        const int i = lds_corank(A, cur.acnt, boff, cur.bcnt, diag);
+        T out[VT];
+        serial_merge<VT>(A, cur.acnt, boff, cur.bcnt, i, diag - i, out);
+        lds_barrier();
+#pragma unroll
+        for (int k = 0; k < VT; ++k)
+            S[t * VT + k] = out[k];
+        lds_barrier();
+
+#pragma unroll
+        for (int q = 0; q < VT / 4; ++q) {
+            const int c = t + NT * q;
+            const int64_t e = cur.o0 + 4 * c;
+            if (4 * c >= cur.cnt)
+                continue;
+            if (4 * c + 4 <= cur.cnt) {
+                if constexpr (sizeof(T) == 4) {
+                    *(int4 *)(kout + e) = *(const int4 *)(S + 4 * c);
+                } else {
+                    const T x0 = S[4 * c], x1 = S[4 * c + 1], x2 = S[4 * c + 2], x3 = S[4 * c + 3];
+                    *(int4 *)(kout + e) =
+                        make_int4(pair_key(x0), pair_key(x1), pair_key(x2), pair_key(x3));
+                    *(int4 *)(vout + e) =
+                        make_int4(pair_val(x0), pair_val(x1), pair_val(x2), pair_val(x3));
+                }
+            } else {
+#pragma unroll
+                for (int q2 = 0; q2 < 4; ++q2)
+                    if (4 * c + q2 < cur.cnt)
+                        store_elem<T>(kout, vout, e + q2, S[4 * c + q2]);
+            }
+        }
+        if (!more)
+            break;
+        g = gn;
+        cur = nxt;
+    }
+}
+
 // ------------------------------------------------------------- launchers
 
 static CorankCtl make_ctl(const CorankOpts &o)
@@ -326,10 +571,72 @@ static hipError_t launch_mp(const int32_t *kin, const int32_t *vin, int32_t *kou
     return hipGetLastError();
 }
 
+int device_cus()
+{
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 256;
+    if (!cus[dev]) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            c <= 0)
+            c = 256;
+        cus[dev] = c;
+    }
+    return cus[dev];
+}
+
+template <int NT, int VT, typename T>
+static hipError_t launch_mpp(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
+                             int64_t n, int64_t run, const int64_t *cr, int occupancy, bool xcd,
+                             hipStream_t s)
+{
+    const int64_t ntiles = (n + NT * VT - 1) / (NT * VT);
+    int occ = occupancy;
+    if (occ <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &occ, (const void *)merge_pass_pipe_kernel<NT, VT, T>, NT, 0) != hipSuccess ||
+            occ <= 0)
+            occ = 1;
+    }
+    int64_t grid = (int64_t)device_cus() * occ;
+    if (grid > ntiles)
+        grid = ntiles;
+    if (xcd)
+        grid = ((grid + 7) / 8) * 8;
+    hipLaunchKernelGGL((merge_pass_pipe_kernel<NT, VT, T>), dim3((unsigned)grid), dim3(NT), 0, s,
+                       kin, vin, kout, vout, n, run, cr, ntiles, xcd ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_merge_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
                              int32_t *kout, int32_t *vout, int64_t n, int64_t run,
-                             const int64_t *cr, hipStream_t s)
+                             const int64_t *cr, int variant, int occupancy, hipStream_t s)
 {
+    // The pipelined kernel moves 16-byte chunks: it needs 16-byte aligned
+    // arrays and at least 16 elements; anything else takes the simple kernel.
+    const bool aligned = ((uintptr_t)kin % 16 == 0) && ((uintptr_t)kout % 16 == 0) &&
+                         (!pairs || (((uintptr_t)vin % 16 == 0) && ((uintptr_t)vout % 16 == 0)));
+    if (variant != 1 && aligned && n >= 16) {
+        const bool xcd = variant == 3;
+        switch (tm) {
+        case 2048:
+            return pairs ? launch_mpp<256, 8, int64_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s)
+                         : launch_mpp<256, 8, int32_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s);
+        case 4096:
+            return pairs ? launch_mpp<256, 16, int64_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s)
+                         : launch_mpp<256, 16, int32_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s);
+        case 8192:
+            return pairs ? launch_mpp<512, 16, int64_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s)
+                         : launch_mpp<512, 16, int32_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s);
+        case 16384:
+            if (!pairs)
+                return launch_mpp<512, 32, int32_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s);
+            break;
+        }
+        return hipErrorInvalidValue;
+    }
     switch (tm) {
     case 2048:
         return pairs ? launch_mp<256, 8, int64_t>(kin, vin, kout, vout, n, run, cr, s)
