@@ -162,13 +162,21 @@ int hvms_corank_i32(const int32_t *d_a, int64_t m, const int32_t *d_b, int64_t k
 /* ------------------------------------------------------------- segmented */
 
 /*
- * Segmented sort: for every s in [0, nseg) sort keys d_in[off[s] .. off[s+1])
- * into d_out at the same positions.  d_offsets is a DEVICE array of nseg+1
- * nondecreasing int64 offsets; n_total = off[nseg] and max_seg (an upper
- * bound on the largest segment) are passed by the host.  Keys outside every
- * segment are copied through unchanged only if they lie in [off[0], n_total).
- * All segments are sorted by one persistent launch (plus binning and, for
- * segments above the block tile, merge passes inside the same launch).
+ * Segmented sort (batched form of the sort, each segment sorted as in Sec.
+ * 2.1): for every s in [0, nseg) write the ascending arrangement of
+ * d_in[off[s] .. off[s+1]) to d_out at the same positions.
+ *   d_offsets  DEVICE array of nseg+1 nondecreasing int64 offsets.
+ *   n_total    must equal off[nseg] (the arrays hold at least n_total keys).
+ *   max_seg    host-side upper bound on the largest segment; it fixes how
+ *              many merge passes are enqueued, so a segment larger than it is
+ *              left unsorted.
+ *   d_out      16-byte aligned (pairs: d_vals_out too).
+ * Elements outside [off[0], off[nseg]) are not written.  A segment whose
+ * offsets fall outside [0, n_total] is treated as empty.  Everything up to
+ * the block tile is sorted by one persistent launch that pulls packed tasks
+ * from an atomic ticket; larger segments add one co-rank and one merge launch
+ * per merge pass.  The call allocates and synchronises nothing, so it can be
+ * captured into a hipGraph.  Workspace: hvms_segmented_workspace_bytes.
  */
 int64_t hvms_segmented_workspace_bytes(int64_t n_total, int64_t nseg, int64_t max_seg,
                                        int32_t pairs, const hvms_options *opt);

@@ -291,4 +291,84 @@ int hvms_corank_i32(const int32_t *d_a, int64_t m, const int32_t *d_b, int64_t k
                                          (hipStream_t)stream));
 }
 
+int64_t hvms_segmented_workspace_bytes(int64_t n_total, int64_t nseg, int64_t max_seg,
+                                       int32_t pairs, const hvms_options *opt)
+{
+    if (n_total < 0 || nseg < 0 || max_seg < 0)
+        return HVMS_ERR_INVALID_ARG;
+    Cfg c;
+    const int st = resolve(opt, pairs != 0, c);
+    if (st)
+        return st;
+    if (nseg == 0)
+        return 0;
+    return seg_layout(n_total, nseg, c.R, c.NT, c.TM, pairs != 0).total;
+}
+
+static int run_segmented(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
+                         const int64_t *off, int64_t nseg, int64_t n_total, int64_t max_seg,
+                         void *ws, size_t ws_bytes, void *stream, const hvms_options *opt)
+{
+    const bool pairs = vin != nullptr;
+    if (nseg < 0 || n_total < 0 || max_seg < 0 || (nseg > 0 && !off) || nseg >= (1ll << 31))
+        return HVMS_ERR_INVALID_ARG;
+    if (n_total > 0 && (!kin || !kout || (pairs && (!vin || !vout))))
+        return HVMS_ERR_INVALID_ARG;
+    Cfg c;
+    int st = resolve(opt, pairs, c);
+    if (st)
+        return st;
+    if (nseg == 0 || n_total == 0)
+        return HVMS_OK;
+    // the merge passes move 16-byte chunks of the output and scratch arrays
+    if (((uintptr_t)kout & 15) || (pairs && ((uintptr_t)vout & 15)))
+        return HVMS_ERR_INVALID_ARG;
+    st = check_ws(ws, ws_bytes, seg_layout(n_total, nseg, c.R, c.NT, c.TM, pairs).total);
+    if (st)
+        return st;
+    const int64_t tile = (int64_t)c.R * c.NT;
+    SegArgs a;
+    a.kin = kin;
+    a.vin = vin;
+    a.kout = kout;
+    a.vout = vout;
+    a.off = off;
+    a.nseg = nseg;
+    a.n_total = n_total;
+    a.passes = max_seg > tile ? ilog2_exact((max_seg + tile - 1) / tile) : 0;
+    a.R = c.R;
+    a.NT = c.NT;
+    a.K = c.K;
+    a.TM = c.TM;
+    a.variant = c.variant;
+    a.occupancy = c.occupancy;
+    a.co = c.co;
+    a.ws = ws;
+    if (a.passes > 0 && n_total < 16)
+        return HVMS_ERR_INVALID_ARG;
+    return hip_status(launch_segmented(a, (hipStream_t)stream));
+}
+
+int hvms_segmented_sort_i32(const int32_t *d_in, int32_t *d_out, const int64_t *d_offsets,
+                            int64_t nseg, int64_t n_total, int64_t max_seg, void *d_ws,
+                            size_t ws_bytes, void *stream, const hvms_options *opt)
+{
+    if (nseg > 0 && n_total > 0 && (!d_in || !d_out))
+        return HVMS_ERR_INVALID_ARG;
+    return run_segmented(d_in, nullptr, d_out, nullptr, d_offsets, nseg, n_total, max_seg, d_ws,
+                         ws_bytes, stream, opt);
+}
+
+int hvms_segmented_sort_pairs_i32(const int32_t *d_keys_in, const int32_t *d_vals_in,
+                                  int32_t *d_keys_out, int32_t *d_vals_out,
+                                  const int64_t *d_offsets, int64_t nseg, int64_t n_total,
+                                  int64_t max_seg, void *d_ws, size_t ws_bytes, void *stream,
+                                  const hvms_options *opt)
+{
+    if (nseg > 0 && n_total > 0 && (!d_keys_in || !d_vals_in || !d_keys_out || !d_vals_out))
+        return HVMS_ERR_INVALID_ARG;
+    return run_segmented(d_keys_in, d_vals_in, d_keys_out, d_vals_out, d_offsets, nseg, n_total,
+                         max_seg, d_ws, ws_bytes, stream, opt);
+}
+
 }  // extern "C"

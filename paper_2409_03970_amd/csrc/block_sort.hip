@@ -62,30 +62,7 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
         }
     }
 
-    column_sort<R>(v);
-    wave_merge<R>(v, lane, wave_levels);
-
-    T *W = S + wave * (64 * R) + lane * R;
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        W[r] = v[r];
-    __syncthreads();
-
-    int run = R << wave_levels;
-    for (int l = 0; l < lds_levels; ++l, run *= 2) {
-        const int o0 = t * R;
-        const int base = o0 & ~(2 * run - 1);
-        const int d = o0 - base;
-        const T *P = S + base;
-        const int i = lds_corank(P, run, run, run, d);
-        T out[R];
-        serial_merge<R>(P, run, run, run, i, d - i, out);
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-            S[o0 + k] = out[k];
-        __syncthreads();
-    }
+    sort_tile_core<R, NT>(S, v, t, wave_levels, lds_levels);
 
     if (tile0 + TILE <= n) {
 #pragma unroll

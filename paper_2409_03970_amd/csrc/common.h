@@ -259,4 +259,41 @@ __device__ __forceinline__ void serial_merge(const T *S, int alen, int boff, int
     }
 }
 
+// Steps a2-a4 on one tile: v holds each lane's R values (for runs shorter
+// than the tile: elements R*lane .. R*lane+R-1 of its wave's slice); sorts
+// the columns, runs `wave_levels` cross-lane merge levels, writes the runs to
+// S in order and merges them `lds_levels` more times in LDS.  On return (after
+// a barrier) S[p] is element p of the tile's sorted runs.
+template <int R, int NT, typename T>
+__device__ __forceinline__ void sort_tile_core(T *S, T (&v)[R], int t, int wave_levels,
+                                               int lds_levels)
+{
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    column_sort<R>(v);
+    wave_merge<R>(v, lane, wave_levels);
+
+    T *W = S + wave * (64 * R) + lane * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        W[r] = v[r];
+    __syncthreads();
+
+    int run = R << wave_levels;
+    for (int l = 0; l < lds_levels; ++l, run *= 2) {
+        const int o0 = t * R;
+        const int base = o0 & ~(2 * run - 1);
+        const int d = o0 - base;
+        const T *P = S + base;
+        const int i = lds_corank(P, run, run, run, d);
+        T out[R];
+        serial_merge<R>(P, run, run, run, i, d - i, out);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            S[o0 + k] = out[k];
+        __syncthreads();
+    }
+}
+
 }  // namespace hvms

@@ -35,4 +35,30 @@ hipError_t launch_corank_list(const int32_t *a, int64_t m, const int32_t *b, int
                               const int64_t *diag, int64_t count, int64_t *out,
                               const CorankOpts &o, hipStream_t s);
 
+inline int ceil_log2_host(int64_t x)
+{
+    int l = 0;
+    while (((int64_t)1 << l) < x)
+        ++l;
+    return l;
+}
+
+// segmented.hip
+struct SegLayout {
+    int64_t ctrl, pieces, tiles, cr, passes, scr_k, scr_v, total, max_tiles, max_pieces;
+};
+SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool pairs);
+
+struct SegArgs {
+    const int32_t *kin, *vin;  // vin == nullptr: keys only
+    int32_t *kout, *vout;
+    const int64_t *off;
+    int64_t nseg, n_total;
+    int passes;                // merge passes the largest segment needs
+    int R, NT, K, TM, variant, occupancy;
+    CorankOpts co;
+    void *ws;
+};
+hipError_t launch_segmented(const SegArgs &a, hipStream_t s);
+
 }  // namespace hvms

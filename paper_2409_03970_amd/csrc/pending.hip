@@ -2,21 +2,6 @@
 #include "hvms.h"
 
 extern "C" {
-int64_t hvms_segmented_workspace_bytes(int64_t, int64_t, int64_t, int32_t, const hvms_options *)
-{
-    return HVMS_ERR_UNSUPPORTED;
-}
-int hvms_segmented_sort_i32(const int32_t *, int32_t *, const int64_t *, int64_t, int64_t, int64_t,
-                            void *, size_t, void *, const hvms_options *)
-{
-    return HVMS_ERR_UNSUPPORTED;
-}
-int hvms_segmented_sort_pairs_i32(const int32_t *, const int32_t *, int32_t *, int32_t *,
-                                  const int64_t *, int64_t, int64_t, int64_t, void *, size_t,
-                                  void *, const hvms_options *)
-{
-    return HVMS_ERR_UNSUPPORTED;
-}
 int hvms_cdf_forward(const float *, const float *, float *, int64_t, void *) { return HVMS_ERR_UNSUPPORTED; }
 int64_t hvms_cdf_workspace_bytes(int64_t) { return HVMS_ERR_UNSUPPORTED; }
 int hvms_cdf_backward(const float *, const float *, const float *, float *, float *, int64_t, void *,

@@ -1,0 +1,507 @@
+// Batched segmented sort: many arrays of uneven sizes, sorted by one
+// persistent launch for everything up to the block tile, plus merge passes
+// for the segments larger than it (steps a1-a6 applied per segment, a8).
+//
+// Plan (all kernels on the caller's stream; no memset, no allocation, no host
+// synchronisation, so the whole call can be captured into a hipGraph):
+//  1. init:     zero the control block.
+//  2. count:    each segment gets a size class.  A segment of s <= TILE keys
+//               goes to bucket X = max(R, 2^ceil(log2 s)); a larger segment is
+//               cut into ceil(s/TILE) pieces of bucket TILE and needs
+//               P_s = ceil(log2(pieces)) merge passes.  Counts are reduced in
+//               LDS, then added to the control block once per workgroup.
+//  3. plan:     one workgroup turns counts into list bases, task numbers
+//               (a task packs TILE/X pieces of one bucket into one tile) and
+//               the tile count of every merge pass.
+//  4. scatter:  pieces go to their bucket lists; the merge tiles of large
+//               segments go to a tile list ordered by P_s descending, so the
+//               tiles of pass p are a prefix of it.
+//  5. block:    persistent kernel; workgroups pull tasks with an atomic
+//               ticket, largest buckets first.  A task gathers its pieces
+//               into LDS (padded with the maximum), sorts every run of X in
+//               place (column sort, cross-lane levels, LDS merges), and
+//               scatters them back: small segments straight to the output,
+//               pieces of large segments to output or scratch by the parity
+//               of P_s.
+//  6. passes:   for p < P_max: co-ranks of pass p's tiles, then the
+//               persistent pipelined merge over the same tile list.
+#include "hvms.h"
+#include "hvms_internal.h"
+#include "merge_common.h"
+
+namespace hvms {
+
+namespace {
+
+constexpr int kMaxBuckets = 16;
+constexpr int kMaxP = 48;
+
+// control block layout (int64 words)
+enum : int {
+    C_CNT = 0,                      // pieces per bucket
+    C_CUR = C_CNT + kMaxBuckets,    // scatter cursors per bucket
+    C_BASE = C_CUR + kMaxBuckets,   // first piece of each bucket
+    C_TASK = C_BASE + kMaxBuckets,  // first task of each bucket
+    C_NTASK = C_TASK + kMaxBuckets, // total tasks
+    C_TICKET,                       // task ticket counter
+    C_LCNT = 80,                    // large segments with P_s == P
+    C_TCNT = C_LCNT + kMaxP,        // merge tiles of those segments
+    C_TCUR = C_TCNT + kMaxP,        // tile-list cursors per P
+    C_TBASE = C_TCUR + kMaxP,       // tile-list base per P
+    C_PASS = C_TBASE + kMaxP,       // tiles of pass p
+    C_WORDS = C_PASS + kMaxP
+};
+
+struct Piece {
+    int64_t off;  // absolute index of the first key
+    int32_t len;  // keys (<= X of its bucket)
+    int32_t dst;  // 0: output, 1: scratch
+};
+
+__device__ __forceinline__ int ceil_log2(int64_t x)
+{
+    int l = 0;
+    while (((int64_t)1 << l) < x)
+        ++l;
+    return l;
+}
+
+struct SegParams {
+    const int64_t *off;
+    int64_t nseg, n_total;
+    int64_t max_pieces, max_tiles;  // list capacities in the workspace
+    int tile_log2, r_log2, nb;  // nb = buckets = tile_log2 - r_log2 + 1
+    int64_t tm;
+};
+
+__device__ __forceinline__ int bucket_of(const SegParams &P, int64_t size)
+{
+    const int l = ceil_log2(size);
+    return (l < P.r_log2 ? P.r_log2 : l) - P.r_log2;
+}
+
+__global__ void seg_init_kernel(unsigned long long *ctrl)
+{
+    for (int i = threadIdx.x; i < C_WORDS; i += blockDim.x)
+        ctrl[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned long long *ctrl)
+{
+    __shared__ unsigned long long cnt[kMaxBuckets], lcnt[kMaxP], tcnt[kMaxP];
+    for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
+        lcnt[i] = 0;
+        tcnt[i] = 0;
+        if (i < kMaxBuckets)
+            cnt[i] = 0;
+    }
+    __syncthreads();
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < P.nseg) {
+        // a segment outside [0, n_total] is treated as empty
+        const int64_t a = P.off[s], e = P.off[s + 1];
+        const int64_t size = (a >= 0 && e <= P.n_total) ? e - a : 0;
+        if (size > 0) {
+            const int64_t tile = (int64_t)1 << P.tile_log2;
+            if (size <= tile) {
+                atomicAdd(&cnt[bucket_of(P, size)], 1ull);
+            } else {
+                const int64_t np = (size + tile - 1) / tile;
+                const int ps = ceil_log2(np);
+                atomicAdd(&cnt[P.nb - 1], (unsigned long long)np);
+                atomicAdd(&lcnt[ps], 1ull);
+                atomicAdd(&tcnt[ps], (unsigned long long)((size + P.tm - 1) / P.tm));
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
+        if (lcnt[i])
+            atomicAdd(&ctrl[C_LCNT + i], lcnt[i]);
+        if (tcnt[i])
+            atomicAdd(&ctrl[C_TCNT + i], tcnt[i]);
+        if (i < kMaxBuckets && cnt[i])
+            atomicAdd(&ctrl[C_CNT + i], cnt[i]);
+    }
+}
+
+__global__ void seg_plan_kernel(SegParams P, unsigned long long *ctrl)
+{
+    if (threadIdx.x != 0)
+        return;
+    unsigned long long pieces = 0, tiles_total = 0;
+    for (int b = 0; b < P.nb; ++b)
+        pieces += ctrl[C_CNT + b];
+    for (int p = 0; p < kMaxP; ++p)
+        tiles_total += ctrl[C_TCNT + p];
+    if (pieces > (unsigned long long)P.max_pieces || tiles_total > (unsigned long long)P.max_tiles) {
+        // inconsistent offsets / n_total: leave every task and pass empty
+        for (int i = 0; i < C_WORDS; ++i)
+            ctrl[i] = 0;
+        return;
+    }
+    unsigned long long base = 0, task = 0;
+    for (int b = P.nb - 1; b >= 0; --b) {  // largest bucket first
+        const unsigned long long slots = (unsigned long long)1 << (P.tile_log2 - (P.r_log2 + b));
+        ctrl[C_BASE + b] = base;
+        ctrl[C_TASK + b] = task;
+        base += ctrl[C_CNT + b];
+        task += (ctrl[C_CNT + b] + slots - 1) / slots;
+    }
+    ctrl[C_NTASK] = task;
+    unsigned long long tb = 0;
+    for (int p = kMaxP - 1; p >= 1; --p) {  // tile list ordered by P descending
+        ctrl[C_TBASE + p] = tb;
+        tb += ctrl[C_TCNT + p];
+    }
+    // pass p covers the segments with P_s > p: a prefix of the tile list
+    for (int p = 0; p < kMaxP; ++p) {
+        unsigned long long t = 0;
+        for (int q = p + 1; q < kMaxP; ++q)
+            t += ctrl[C_TCNT + q];
+        ctrl[C_PASS + p] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned long long *ctrl,
+                                                          Piece *pieces, int2 *tiles,
+                                                          int32_t *passes)
+{
+    __shared__ unsigned long long cnt[kMaxBuckets], bbase[kMaxBuckets], tcnt[kMaxP], tbase[kMaxP];
+    for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
+        tcnt[i] = 0;
+        if (i < kMaxBuckets)
+            cnt[i] = 0;
+    }
+    __syncthreads();
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tile = (int64_t)1 << P.tile_log2;
+    int64_t size = 0, np = 0, nt = 0, o = 0;
+    int b = -1, ps = 0;
+    unsigned long long mine = 0, tmine = 0;
+    if (s < P.nseg) {
+        o = P.off[s];
+        const int64_t e = P.off[s + 1];
+        size = (o >= 0 && e <= P.n_total) ? e - o : 0;
+        if (size > 0) {
+            if (size <= tile) {
+                b = bucket_of(P, size);
+                np = 1;
+            } else {
+                b = P.nb - 1;
+                np = (size + tile - 1) / tile;
+                ps = ceil_log2(np);
+                nt = (size + P.tm - 1) / P.tm;
+                tmine = atomicAdd(&tcnt[ps], (unsigned long long)nt);
+            }
+            mine = atomicAdd(&cnt[b], (unsigned long long)np);
+        }
+        passes[s] = ps;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
+        if (tcnt[i])
+            tbase[i] = ctrl[C_TBASE + i] + atomicAdd(&ctrl[C_TCUR + i], tcnt[i]);
+        if (i < kMaxBuckets && cnt[i])
+            bbase[i] = ctrl[C_BASE + i] + atomicAdd(&ctrl[C_CUR + i], cnt[i]);
+    }
+    __syncthreads();
+    if (b >= 0) {
+        const int64_t first = bbase[b] + mine;
+        const int dst = (ps & 1) ? 1 : 0;
+        for (int64_t i = 0; i < np && first + i < P.max_pieces; ++i) {
+            Piece pc;
+            pc.off = o + i * tile;
+            const int64_t rem = size - i * tile;
+            pc.len = (int32_t)(rem < tile ? rem : tile);
+            pc.dst = dst;
+            pieces[first + i] = pc;
+        }
+        if (nt) {
+            const int64_t tf = tbase[ps] + tmine;
+            for (int64_t j = 0; j < nt && tf + j < P.max_tiles; ++j)
+                tiles[tf + j] = make_int2((int)s, (int)j);
+        }
+    }
+}
+
+// Persistent block stage: one packed task per iteration.
+template <int R, int NT, typename T>
+__global__ __launch_bounds__(NT) void seg_block_kernel(SegParams P, unsigned long long *ctrl,
+                                                       const Piece *__restrict__ pieces,
+                                                       const int32_t *__restrict__ ik,
+                                                       const int32_t *__restrict__ iv,
+                                                       int32_t *__restrict__ ok,
+                                                       int32_t *__restrict__ ov,
+                                                       int32_t *__restrict__ sk,
+                                                       int32_t *__restrict__ sv, int wave_max)
+{
+    constexpr int TILE = R * NT;
+    __shared__ T S[TILE];
+    __shared__ int64_t s_off[NT];
+    __shared__ int32_t s_len[NT], s_dst[NT];
+    __shared__ unsigned long long s_ticket;
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const unsigned long long ntask = ctrl[C_NTASK];
+
+    for (;;) {
+        if (t == 0)
+            s_ticket = atomicAdd(&ctrl[C_TICKET], 1ull);
+        __syncthreads();
+        const unsigned long long ticket = s_ticket;
+        if (ticket >= ntask)
+            break;
+        int b = P.nb - 1;
+        while (b > 0 && ctrl[C_TASK + b - 1] <= ticket)
+            --b;
+        const int xlog = P.r_log2 + b;
+        const int slots = 1 << (P.tile_log2 - xlog);
+        const unsigned long long first = ctrl[C_BASE + b] + (ticket - ctrl[C_TASK + b]) * slots;
+        const unsigned long long avail = ctrl[C_CNT + b] - (ticket - ctrl[C_TASK + b]) * slots;
+        const int npieces = (int)(avail < slots ? avail : slots);
+        if (t < npieces) {
+            const Piece pc = pieces[first + t];
+            s_off[t] = pc.off;
+            s_len[t] = pc.len;
+            s_dst[t] = pc.dst;
+        }
+        __syncthreads();
+
+        // gather: slot i of X keys holds piece i, padded with the maximum
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int p = t + NT * k;
+            const int slot = p >> xlog, j = p & ((1 << xlog) - 1);
+            T x = Traits<T>::kMax;
+            if (slot < npieces && j < s_len[slot])
+                x = load_elem<T>(ik, iv, s_off[slot] + j);
+            S[p] = x;
+        }
+        __syncthreads();
+        T v[R];
+        const T *W = S + wave * (64 * R) + lane * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            v[r] = W[r];
+        __syncthreads();
+        const int levels = xlog - P.r_log2;
+        const int K = levels < wave_max ? levels : wave_max;
+        sort_tile_core<R, NT>(S, v, t, K, levels - K);
+
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int p = t + NT * k;
+            const int slot = p >> xlog, j = p & ((1 << xlog) - 1);
+            if (slot < npieces && j < s_len[slot]) {
+                const bool scr = s_dst[slot] != 0;
+                store_elem<T>(scr ? sk : ok, scr ? sv : ov, s_off[slot] + j, S[p]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void seg_corank_kernel(SegMap map, int64_t run, int64_t tm,
+                                                         int64_t *__restrict__ cr, CorankCtl c)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < map.count())
+        tile_corank<T>(map, q, run, tm, cr, c);
+}
+
+template <int NT, int VT, typename T>
+__global__ __launch_bounds__(NT) void seg_merge_kernel(SegMap map, int64_t run,
+                                                       const int64_t *__restrict__ cr,
+                                                       int64_t n_abs, int xcd_group)
+{
+    merge_pipe_body<NT, VT, T>(map, run, cr, n_abs, xcd_group);
+}
+
+int64_t a256(int64_t b) { return (b + 255) & ~(int64_t)255; }
+
+}  // namespace
+
+SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool pairs)
+{
+    SegLayout L{};
+    const int64_t tile = (int64_t)R * NT;
+    const int64_t max_pieces = nseg + 2 * (n_total / tile) + 2;
+    const int64_t max_tiles = n_total / TM + n_total / tile + 2;
+    int64_t o = 0;
+    L.ctrl = o;
+    o += a256(C_WORDS * 8);
+    L.pieces = o;
+    o += a256(max_pieces * (int64_t)sizeof(Piece));
+    L.tiles = o;
+    o += a256(max_tiles * 8);
+    L.cr = o;
+    o += a256((max_tiles + 1) * 8);
+    L.passes = o;
+    o += a256(nseg * 4);
+    L.scr_k = o;
+    o += a256(n_total * 4);
+    L.scr_v = o;
+    if (pairs)
+        o += a256(n_total * 4);
+    L.total = o;
+    L.max_tiles = max_tiles;
+    L.max_pieces = max_pieces;
+    return L;
+}
+
+template <int R, int NT, typename T>
+static hipError_t launch_seg_block(const SegParams &P, unsigned long long *ctrl, const Piece *pieces,
+                                   const int32_t *ik, const int32_t *iv, int32_t *ok, int32_t *ov,
+                                   int32_t *sk, int32_t *sv, int wave_max, hipStream_t s)
+{
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)seg_block_kernel<R, NT, T>,
+                                                     NT, 0) != hipSuccess ||
+        occ <= 0)
+        occ = 1;
+    const unsigned grid = (unsigned)(device_cus() * occ);
+    hipLaunchKernelGGL((seg_block_kernel<R, NT, T>), dim3(grid), dim3(NT), 0, s, P, ctrl, pieces,
+                       ik, iv, ok, ov, sk, sv, wave_max);
+    return hipGetLastError();
+}
+
+template <int NT, int VT, typename T>
+static hipError_t launch_seg_merge(const SegMap &map, int64_t run, const int64_t *cr,
+                                   int64_t n_abs, int64_t max_tiles, int occupancy, bool xcd,
+                                   hipStream_t s)
+{
+    int occ = occupancy;
+    if (occ <= 0 &&
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)seg_merge_kernel<NT, VT, T>,
+                                                      NT, 0) != hipSuccess ||
+         occ <= 0))
+        occ = 1;
+    int64_t grid = (int64_t)device_cus() * occ;
+    if (grid > max_tiles)
+        grid = max_tiles;
+    if (xcd)
+        grid = ((grid + 7) / 8) * 8;
+    hipLaunchKernelGGL((seg_merge_kernel<NT, VT, T>), dim3((unsigned)grid), dim3(NT), 0, s, map,
+                       run, cr, n_abs, xcd ? 1 : 0);
+    return hipGetLastError();
+}
+
+static hipError_t launch_seg_block_any(int R, int NT, bool pairs, const SegParams &P,
+                                       unsigned long long *ctrl, const Piece *pieces, const SegArgs &a,
+                                       int32_t *sk, int32_t *sv, hipStream_t s)
+{
+#define HVMS_SB(RR, NN)                                                                         \
+    if (R == RR && NT == NN)                                                                    \
+        return pairs ? launch_seg_block<RR, NN, int64_t>(P, ctrl, pieces, a.kin, a.vin, a.kout, \
+                                                         a.vout, sk, sv, a.K, s)                 \
+                     : launch_seg_block<RR, NN, int32_t>(P, ctrl, pieces, a.kin, a.vin, a.kout, \
+                                                         a.vout, sk, sv, a.K, s);
+    HVMS_SB(16, 256)
+    HVMS_SB(16, 512)
+    HVMS_SB(16, 1024)
+    HVMS_SB(8, 256)
+    HVMS_SB(8, 512)
+    HVMS_SB(8, 1024)
+    HVMS_SB(32, 256)
+    HVMS_SB(32, 512)
+#undef HVMS_SB
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
+{
+    const bool pairs = a.vin != nullptr;
+    const int64_t tile = (int64_t)a.R * a.NT;
+    const int tile_log2 = ceil_log2_host(tile), r_log2 = ceil_log2_host(a.R);
+    const SegLayout L = seg_layout(a.n_total, a.nseg, a.R, a.NT, a.TM, pairs);
+    SegParams P;
+    P.off = a.off;
+    P.nseg = a.nseg;
+    P.n_total = a.n_total;
+    P.max_pieces = L.max_pieces;
+    P.max_tiles = L.max_tiles;
+    P.tile_log2 = tile_log2;
+    P.r_log2 = r_log2;
+    P.nb = tile_log2 - r_log2 + 1;
+    P.tm = a.TM;
+    char *ws = (char *)a.ws;
+    unsigned long long *ctrl = (unsigned long long *)(ws + L.ctrl);
+    Piece *pieces = (Piece *)(ws + L.pieces);
+    int2 *tiles = (int2 *)(ws + L.tiles);
+    int64_t *cr = (int64_t *)(ws + L.cr);
+    int32_t *passes = (int32_t *)(ws + L.passes);
+    int32_t *sk = (int32_t *)(ws + L.scr_k);
+    int32_t *sv = pairs ? (int32_t *)(ws + L.scr_v) : nullptr;
+
+    hipLaunchKernelGGL(seg_init_kernel, dim3(1), dim3(256), 0, s, ctrl);
+    const unsigned sb = (unsigned)((a.nseg + 255) / 256);
+    hipLaunchKernelGGL(seg_count_kernel, dim3(sb), dim3(256), 0, s, P, ctrl);
+    hipLaunchKernelGGL(seg_plan_kernel, dim3(1), dim3(64), 0, s, P, ctrl);
+    hipLaunchKernelGGL(seg_scatter_kernel, dim3(sb), dim3(256), 0, s, P, ctrl, pieces, tiles,
+                       passes);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+
+    e = launch_seg_block_any(a.R, a.NT, pairs, P, ctrl, pieces, a, sk, sv, s);
+    if (e != hipSuccess)
+        return e;
+
+    for (int p = 0; p < a.passes; ++p) {
+        SegMap map;
+        map.outk = a.kout;
+        map.outv = a.vout;
+        map.scrk = sk;
+        map.scrv = sv;
+        map.off = a.off;
+        map.tiles = tiles;
+        map.passes = passes;
+        map.pass_tiles = (const int64_t *)(ctrl + C_PASS);
+        map.p = p;
+        const int64_t run = tile << p;
+        CorankCtl c;
+        c.mode = a.co.mode;
+        c.radius_log2 = a.co.radius_log2;
+        c.cdf = a.co.cdf;
+        c.stats = a.co.stats;
+        const unsigned cb = (unsigned)((L.max_tiles + 255) / 256);
+        if (pairs)
+            hipLaunchKernelGGL(seg_corank_kernel<int64_t>, dim3(cb), dim3(256), 0, s, map, run,
+                               (int64_t)a.TM, cr, c);
+        else
+            hipLaunchKernelGGL(seg_corank_kernel<int32_t>, dim3(cb), dim3(256), 0, s, map, run,
+                               (int64_t)a.TM, cr, c);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        const bool xcd = a.variant == 3;
+        switch (a.TM) {
+        case 2048:
+            e = pairs ? launch_seg_merge<256, 8, int64_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s)
+                      : launch_seg_merge<256, 8, int32_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s);
+            break;
+        case 4096:
+            e = pairs ? launch_seg_merge<256, 16, int64_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s)
+                      : launch_seg_merge<256, 16, int32_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s);
+            break;
+        case 8192:
+            e = pairs ? launch_seg_merge<512, 16, int64_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s)
+                      : launch_seg_merge<512, 16, int32_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s);
+            break;
+        case 16384:
+            e = pairs ? hipErrorInvalidValue
+                      : launch_seg_merge<512, 32, int32_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s);
+            break;
+        default:
+            e = hipErrorInvalidValue;
+        }
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace hvms

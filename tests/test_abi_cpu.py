@@ -93,3 +93,21 @@ def test_every_option_set_of_the_gpu_tests_is_accepted():
         assert L.hvms_sort_workspace_bytes(1 << 20, 0, hv._opts(o)) >= 0, o
         assert L.hvms_sort_runs_i32(FAKE, FAKE, 0, 4 if o["keys_per_lane"] <= 16 else 5,
                                     None, hv._opts(o)) == 0, o
+
+
+def test_segmented_workspace_and_errors():
+    L = hv.lib()
+    assert L.hvms_segmented_workspace_bytes(0, 0, 0, 0, None) == 0
+    a = L.hvms_segmented_workspace_bytes(1 << 20, 100, 65536, 0, None)
+    b = L.hvms_segmented_workspace_bytes(1 << 20, 100, 65536, 1, None)
+    assert a >= 4 * (1 << 20) and b >= a + 4 * (1 << 20) and a % 256 == 0
+    assert L.hvms_segmented_workspace_bytes(-1, 1, 1, 0, None) == -1
+    # nseg == 0 and n_total == 0 are no-ops
+    assert L.hvms_segmented_sort_i32(None, None, None, 0, 0, 0, None, 0, None, None) == 0
+    # null offsets with segments, missing workspace, misaligned output
+    assert L.hvms_segmented_sort_i32(FAKE, FAKE, None, 3, 100, 50, None, 0, None, None) == -1
+    assert L.hvms_segmented_sort_i32(FAKE, FAKE, FAKE, 3, 100, 50, None, 0, None, None) == -2
+    assert L.hvms_segmented_sort_i32(FAKE, ctypes.c_void_p(0x100004), FAKE, 3, 100, 50, FAKE,
+                                     1 << 30, None, None) == -1
+    assert L.hvms_segmented_sort_pairs_i32(FAKE, None, FAKE, FAKE, FAKE, 3, 100, 50, FAKE,
+                                           1 << 30, None, None) == -1

@@ -1,0 +1,166 @@
+"""GPU parity of the batched segmented sort against the CPU oracle, through the
+C ABI, including replays of a captured HIP graph."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2409_03970_amd as hv
+from paper_2409_03970_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _run(sizes, dist="uniform", seed=0, opts=None, pairs=False):
+    sizes = torch.as_tensor(sizes, dtype=torch.int64)
+    offs = inputs.offsets_from_sizes(sizes)
+    n = int(offs[-1])
+    k = inputs.keys(n, dist, seed=seed, device=DEV)
+    offs_np = offs.numpy()
+    if pairs:
+        v = torch.cat([torch.arange(int(s), dtype=torch.int32) for s in sizes.tolist()]).to(DEV) \
+            if n else torch.empty(0, dtype=torch.int32, device=DEV)
+        ko, vo = hv.segmented_sort_pairs(k, v, offs, opts=opts)
+        ek, ev = oracle.segmented_sort_pairs(k.cpu().numpy(), v.cpu().numpy(), offs_np)
+        assert np.array_equal(ko.cpu().numpy(), ek) and np.array_equal(vo.cpu().numpy(), ev)
+    else:
+        y = hv.segmented_sort(k, offs, opts=opts)
+        assert np.array_equal(y.cpu().numpy(), oracle.segmented_sort(k.cpu().numpy(), offs_np))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_log_uniform_sizes(seed):
+    _say("segmented log-uniform", seed)
+    _run(inputs.log_uniform_sizes(3000, 1, 65536, seed=seed), seed=seed)
+
+
+def test_edge_sizes():
+    # empty, one, around the lane / wave / tile sizes and several merge passes
+    sizes = [0, 1, 0, 2, 15, 16, 17, 31, 33, 1023, 1024, 1025, 8191, 8192, 8193, 0, 16383,
+             16384, 16385, 40000, 65536, 65537, 131072 + 5, 3, 0]
+    _run(sizes, seed=1)
+    _run(sizes[::-1], dist="distinct16", seed=2)
+
+
+def test_single_segment_equals_plain_sort():
+    n = 300007
+    k = inputs.keys(n, "zipf", seed=3, device=DEV)
+    y = hv.segmented_sort(k, torch.tensor([0, n]))
+    assert torch.equal(y, hv.sort(k))
+
+
+def test_all_empty_and_none():
+    k = torch.empty(0, dtype=torch.int32, device=DEV)
+    assert hv.segmented_sort(k, torch.zeros(5, dtype=torch.int64)).numel() == 0
+    assert hv.segmented_sort(k, torch.zeros(1, dtype=torch.int64)).numel() == 0
+
+
+def test_keys_outside_segments_untouched():
+    n = 50000
+    k = inputs.keys(n, "uniform", seed=4, device=DEV)
+    offs = torch.tensor([100, 5000, 5000, 30000, 49000], dtype=torch.int64)
+    out = torch.full_like(k, -7)
+    hv.segmented_sort(k, offs, out=out)
+    o = out.cpu().numpy()
+    assert np.all(o[:100] == -7) and np.all(o[49000:] == -7)
+    want = oracle.segmented_sort(k.cpu().numpy(), offs.numpy())
+    assert np.array_equal(o[100:49000], want[100:49000])
+
+
+@pytest.mark.parametrize("dist", ["distinct16", "sorted", "reverse", "zipf"])
+def test_distributions(dist):
+    _run(inputs.log_uniform_sizes(800, 1, 40000, seed=5), dist=dist, seed=5)
+
+
+@pytest.mark.parametrize("opt", [dict(keys_per_lane=R, block_threads=NT, merge_tile=TM, wave_levels=K + 1,
+                                      merge_variant=V)
+                                 for R, NT in [(16, 256), (16, 512), (16, 1024), (8, 512), (32, 256), (32, 512)]
+                                 for TM in (2048, 4096, 8192) if TM <= 2 * R * NT
+                                 for K in (6, 2) for V in (2, 3)],
+                         ids=lambda o: "R{keys_per_lane}_NT{block_threads}_TM{merge_tile}_K{wave_levels}_V{merge_variant}".format(**o))
+def test_every_tuning(opt):
+    _run(inputs.log_uniform_sizes(400, 1, 70000, seed=6), seed=6, opts=opt)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "distinct16"])
+def test_pairs(dist):
+    _say("segmented pairs", dist)
+    _run(inputs.log_uniform_sizes(600, 1, 50000, seed=7), dist=dist, seed=7, pairs=True)
+
+
+@pytest.mark.parametrize("opt", [dict(keys_per_lane=16, block_threads=256, merge_tile=4096),
+                                 dict(keys_per_lane=8, block_threads=1024, merge_tile=8192),
+                                 dict(keys_per_lane=32, block_threads=512, merge_tile=2048)])
+def test_pairs_tunings(opt):
+    _run(inputs.log_uniform_sizes(300, 1, 40000, seed=8), dist="zipf", seed=8, pairs=True, opts=opt)
+
+
+def test_offsets_on_device_and_in_place():
+    sizes = inputs.log_uniform_sizes(500, 1, 30000, seed=9)
+    offs = inputs.offsets_from_sizes(sizes)
+    n = int(offs[-1])
+    k = inputs.keys(n, "uniform", seed=9, device=DEV)
+    want = oracle.segmented_sort(k.cpu().numpy(), offs.numpy())
+    hv.segmented_sort(k, offs.to(DEV), out=k)
+    assert np.array_equal(k.cpu().numpy(), want)
+
+
+def test_graph_capture_replays():
+    sizes = inputs.log_uniform_sizes(2000, 1, 65536, seed=10)
+    offs = inputs.offsets_from_sizes(sizes)
+    n = int(offs[-1])
+    k = inputs.keys(n, "uniform", seed=10, device=DEV)
+    d_off = offs.to(DEV)
+    out = torch.empty_like(k)
+    max_seg = int(sizes.max())
+    ws = torch.empty(hv.lib().hvms_segmented_workspace_bytes(n, sizes.numel(), max_seg, 0, None),
+                     dtype=torch.uint8, device=DEV)
+    eager = torch.empty_like(k)
+    hv.hvms_segmented_sort_i32(k, eager, d_off, n, max_seg, ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(eager.cpu().numpy(), oracle.segmented_sort(k.cpu().numpy(), offs.numpy()))
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            hv.hvms_segmented_sort_i32(k, out, d_off, n, max_seg, ws)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(4):
+        out.fill_(-1)
+        junk = hv.sort(inputs.keys(70000, "zipf", seed=rep, device=DEV))   # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        assert junk.numel() == 70000
+
+
+def test_full_size_200k_segments():
+    # 200,000 segments, sizes log-uniform in [1, 65536] (about 1.18e9 keys)
+    sizes = inputs.log_uniform_sizes(200000, 1, 65536, seed=0)
+    offs = inputs.offsets_from_sizes(sizes)
+    n = int(offs[-1])
+    _say("full-size segmented, keys:", n)
+    k = inputs.keys(n, "uniform", seed=3, device=DEV)
+    y = hv.segmented_sort(k, offs)
+    torch.cuda.synchronize()
+    d_off = offs.to(DEV)
+    # every segment nondecreasing: only descents allowed are at segment starts
+    desc = torch.nonzero(y[1:] < y[:-1]).flatten() + 1
+    starts = torch.zeros(n + 1, dtype=torch.bool, device=DEV)
+    starts[d_off] = True
+    assert bool(starts[desc].all())
+    ks, ys = k.cpu().numpy(), y.cpu().numpy()
+    offs_np = offs.numpy()
+    # per-segment multisets: the whole array's hash and every sampled segment exactly
+    assert oracle.multiset_hash(ys) == oracle.multiset_hash(ks)
+    rng = np.random.default_rng(0)
+    for s in rng.choice(sizes.numel(), 300, replace=False).tolist() + [int(sizes.argmax())]:
+        a, b = offs_np[s], offs_np[s + 1]
+        assert np.array_equal(ys[a:b], oracle.sort(ks[a:b])), s
