@@ -214,6 +214,12 @@ int hvms_cdf_adam_step(float *d_params, float *d_m, float *d_v, const float *d_g
                        int32_t step, float lr, float beta1, float beta2, float eps,
                        void *stream);
 
+/* Training sample: d_out[k] = d_keys[SplitMix64(seed, k) mod n] for k < m,
+ * where SplitMix64(seed, k) is output k (from 0) of Steele, Lea and Flood's
+ * SplitMix64 generator seeded with `seed` (a sample with replacement). */
+int hvms_cdf_sample_i32(const int32_t *d_keys, int64_t n, int64_t m, uint64_t seed,
+                        int32_t *d_out, void *stream);
+
 /*
  * Train the model on a sorted sample: d_sorted[0..m) ascending keys; the
  * target of the i-th key is i/m.  Runs `steps` Adam steps (lr, betas 0.9 /

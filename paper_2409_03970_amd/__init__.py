@@ -20,6 +20,7 @@ __all__ = [
     "hvms_cdf_forward", "hvms_cdf_backward", "hvms_cdf_adam_step", "hvms_cdf_train",
     "sort", "sort_pairs", "sort_runs", "merge_pass", "corank", "segmented_sort",
     "segmented_sort_pairs", "cdf_forward", "cdf_backward", "cdf_adam_step", "cdf_train",
+    "hvms_cdf_sample_i32", "cdf_sample", "fit_cdf_model",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -84,6 +85,7 @@ _SIGS = {
     "hvms_cdf_adam_step": ([_vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _vp], _i32),
     "hvms_cdf_train_workspace_bytes": ([_i64], _i64),
     "hvms_cdf_train": ([_vp, _vp, _vp, _vp, _i64, _i64, _i32, _f32, _u64, _vp, _sz, _vp], _i32),
+    "hvms_cdf_sample_i32": ([_vp, _i64, _i64, _u64, _vp, _vp], _i32),
 }
 
 _lib = None
@@ -246,6 +248,12 @@ def hvms_cdf_train(params, m, v, sorted_keys, batch, steps, lr, seed, ws=None, s
         int(seed) & 0xFFFFFFFFFFFFFFFF, p, b, _stream(stream)))
 
 
+def hvms_cdf_sample_i32(keys, m, seed, out, stream=None):
+    _check("hvms_cdf_sample_i32", lib().hvms_cdf_sample_i32(
+        _ptr(keys, torch.int32), keys.numel(), int(m), int(seed) & 0xFFFFFFFFFFFFFFFF,
+        _ptr(out, torch.int32), _stream(stream)))
+
+
 # -------------------------------------------------- allocating conveniences
 
 def sort(keys, out=None, opts=None, stream=None):
@@ -331,6 +339,26 @@ def cdf_backward(params, x, t, stream=None):
 def cdf_adam_step(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
                   stream=None):
     hvms_cdf_adam_step(params, m, v, grad, step, lr, beta1, beta2, eps, stream)
+
+
+def cdf_sample(keys, m, seed=0, stream=None):
+    out = torch.empty(int(m), dtype=torch.int32, device=keys.device)
+    hvms_cdf_sample_i32(keys, m, seed, out, stream)
+    return out
+
+
+def fit_cdf_model(keys, frac=0.01, steps=400, batch=65536, lr=1e-3, seed=0, init=None,
+                  stream=None):
+    """The learned part end to end on the device: draw frac * n keys, sort the
+    sample with this library's sort, train the CDF model on it with the
+    library's forward/backward/Adam kernels.  Returns the fp32 parameters."""
+    from . import inputs
+    m = max(2, int(keys.numel() * frac))
+    sample = cdf_sample(keys, m, seed, stream)
+    sample = sort(sample, out=sample, stream=stream)
+    params = (inputs.mlp_init(seed) if init is None else init).to(keys.device).contiguous()
+    cdf_train(params, sample, batch=min(batch, m), steps=steps, lr=lr, seed=seed, stream=stream)
+    return params
 
 
 def cdf_train(params, sorted_keys, batch=65536, steps=500, lr=1e-3, seed=0, stream=None):

@@ -12,6 +12,12 @@ namespace {
 
 thread_local int g_last_hip = 0;
 
+}  // namespace
+
+void hvms::set_last_hip_error(int e) { g_last_hip = e; }
+
+namespace {
+
 int hip_status(hipError_t e)
 {
     if (e == hipSuccess)

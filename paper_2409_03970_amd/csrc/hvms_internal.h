@@ -6,6 +6,9 @@
 
 namespace hvms {
 
+// abi.hip: the hipError_t reported by hvms_last_hip_error (thread-local)
+void set_last_hip_error(int e);
+
 struct CorankOpts {
     int mode;
     int radius_log2;

@@ -6,6 +6,7 @@
 #pragma once
 
 #include "common.h"
+#include "mlp_common.h"
 
 namespace hvms {
 
@@ -33,32 +34,6 @@ __device__ __forceinline__ int64_t binary_corank(FA A, FB B, int64_t d, int64_t 
             lo = mid + 1;
     }
     return lo;
-}
-
-// CDF model forward in fp32: 1 -> 32 -> 32 -> 1 with ReLU.
-__device__ float cdf_eval(const float *__restrict__ p, float x)
-{
-    const float *W1 = p, *b1 = p + 32, *W2 = p + 64, *b2 = p + 64 + 1024, *W3 = p + 64 + 1024 + 32;
-    const float b3 = p[64 + 1024 + 64];
-    float h1[32];
-#pragma unroll
-    for (int u = 0; u < 32; ++u)
-        h1[u] = fmaxf(fmaf(W1[u], x, b1[u]), 0.0f);
-    float y = b3;
-#pragma unroll 4
-    for (int o = 0; o < 32; ++o) {
-        float z = b2[o];
-#pragma unroll
-        for (int u = 0; u < 32; ++u)
-            z = fmaf(W2[o * 32 + u], h1[u], z);
-        y = fmaf(W3[o], fmaxf(z, 0.0f), y);
-    }
-    return y;
-}
-
-__device__ __forceinline__ float key_to_unit(int32_t k)
-{
-    return (float)((double)k + 2147483648.0) * (1.0f / 4294967296.0f);
 }
 
 // Prediction of the co-rank of diagonal d for runs A (m) and B (k).

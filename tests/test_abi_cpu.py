@@ -26,7 +26,7 @@ def _declared():
 
 def test_every_declared_symbol_is_exported():
     names = _declared()
-    assert len(names) == 18
+    assert len(names) == 19
     L = hv.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -111,3 +111,18 @@ def test_segmented_workspace_and_errors():
                                      1 << 30, None, None) == -1
     assert L.hvms_segmented_sort_pairs_i32(FAKE, None, FAKE, FAKE, FAKE, 3, 100, 50, FAKE,
                                            1 << 30, None, None) == -1
+
+
+def test_cdf_argument_errors():
+    L = hv.lib()
+    assert L.hvms_cdf_forward(FAKE, FAKE, FAKE, 0, None) == 0
+    assert L.hvms_cdf_forward(None, FAKE, FAKE, 5, None) == -1
+    assert L.hvms_cdf_workspace_bytes(4096) > 4096 * 4 * 132
+    assert L.hvms_cdf_backward(FAKE, FAKE, FAKE, FAKE, FAKE, 0, FAKE, 1 << 30, None) == -1
+    assert L.hvms_cdf_backward(FAKE, FAKE, FAKE, FAKE, FAKE, 100, None, 0, None) == -2
+    assert L.hvms_cdf_adam_step(FAKE, FAKE, FAKE, FAKE, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert L.hvms_cdf_adam_step(FAKE, FAKE, FAKE, FAKE, 1, 1e-3, 1.0, 0.999, 1e-8, None) == -1
+    assert L.hvms_cdf_train_workspace_bytes(0) == -1
+    assert L.hvms_cdf_train(FAKE, FAKE, FAKE, FAKE, 0, 10, 1, 1e-3, 0, FAKE, 1 << 30, None) == -1
+    assert L.hvms_cdf_sample_i32(FAKE, 0, 5, 1, FAKE, None) == -1
+    assert L.hvms_cdf_sample_i32(FAKE, 10, 0, 1, FAKE, None) == 0
