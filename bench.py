@@ -65,6 +65,180 @@ def cpu_baseline(dists, log2n, seed=0, sample_log2=24):
                       f"oracle merge sort; {total_s:.1f} s of CPU time"}
 
 
+def _median_ms(fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def _mode_stats(x, out, ws, opts, params, mode, radius=12):
+    st = torch.zeros(8, dtype=torch.int64, device=x.device)
+    o = dict(opts, corank_mode=mode, radius_log2=radius, cdf_params=params)
+    ms = _median_ms(lambda: hv.hvms_sort_i32(x, out, ws, opts=o))
+    o["stats"] = st
+    hv.hvms_sort_i32(x, out, ws, opts=o)
+    torch.cuda.synchronize()
+    c = st.cpu().tolist()
+    r = {"ms": round(ms, 3), "gkeys_per_s": round(x.numel() / ms / 1e6, 3),
+         "probes_per_corank": round(c[1] / max(c[0], 1), 2)}
+    if mode != hv.CORANK_BINARY:
+        r.update(fallback_rate=round(c[2] / max(c[0], 1), 4),
+                 mean_abs_err=round(c[3] / max(c[0], 1), 1), max_err=int(c[4]))
+    return r
+
+
+def corank_modes(xs, dists, out, ws, opts):
+    """Binary vs learned vs linear co-rank on the same 2^28 inputs."""
+    res = {}
+    for x, d in zip(xs, dists):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        params = hv.fit_cdf_model(x, frac=0.01, steps=300, batch=65536, lr=3e-3, seed=1)
+        t1.record()
+        torch.cuda.synchronize()
+        r = {"train_ms": round(t0.elapsed_time(t1), 2)}
+        for name, mode in (("binary", hv.CORANK_BINARY), ("learned", hv.CORANK_LEARNED),
+                           ("linear", hv.CORANK_LINEAR)):
+            r[name] = _mode_stats(x, out, ws, opts, params, mode)
+        res[d] = r
+    return res
+
+
+def pairs_bench(n):
+    """Key-value sort of 2^28 (key, original index) pairs."""
+    dev = torch.device("cuda", 0)
+    k, v = inputs.pairs(n, "uniform", seed=0, device=dev)
+    ko, vo = torch.empty_like(k), torch.empty_like(v)
+    from paper_2409_03970_amd import tune
+    opts = tune.tuned_options("sort_pairs", n) or {}
+    ws = hv._workspace(hv.lib().hvms_sort_workspace_bytes(n, 1, hv._opts(opts)), dev)
+    tile = (opts.get("keys_per_lane") or 16) * (opts.get("block_threads") or 512)
+    passes = int(np.ceil(np.log2(-(-n // tile))))
+    ev = make_events(2 + 2 * passes)
+    ms = _median_ms(lambda: hv.hvms_sort_pairs_i32(k, v, ko, vo, ws, opts=opts))
+    hv.hvms_sort_pairs_i32(k, v, ko, vo, ws, opts=dict(opts, events=ev))
+    torch.cuda.synchronize()
+    pm = [ev[2 + 2 * p].elapsed_time(ev[3 + 2 * p]) for p in range(passes)]
+    # certificate: keys nondecreasing and every payload still points at its key
+    ok = bool((ko[1:] >= ko[:-1]).all()) and bool(torch.equal(k[vo.long()], ko))
+    return {"ms": round(ms, 3), "gkeys_per_s": round(n / ms / 1e6, 3), "options": opts,
+            "merge_pass_gbs_mean": round(16.0 * n / (np.mean(pm) / 1e3) / 1e9, 1) if pm else None,
+            "certificate_ok": ok}
+
+
+def batched_bench():
+    """200,000 arrays, sizes log-uniform in [1, 65536]: one batched call
+    (eager and as a replayed HIP graph) against one plain sort per array."""
+    dev = torch.device("cuda", 0)
+    sizes = inputs.log_uniform_sizes(200000, 1, 65536, seed=0)
+    offs = inputs.offsets_from_sizes(sizes)
+    n = int(offs[-1])
+    d_off = offs.to(dev)
+    max_seg = int(sizes.max())
+    k = inputs.keys(n, "uniform", seed=3, device=dev)
+    out = torch.empty_like(k)
+    from paper_2409_03970_amd import tune
+    opts = tune.tuned_options("segmented", n) or {}
+    ws = hv._workspace(hv.lib().hvms_segmented_workspace_bytes(n, sizes.numel(), max_seg, 0,
+                                                                 hv._opts(opts)), dev)
+    eager_ms = _median_ms(lambda: hv.hvms_segmented_sort_i32(k, out, d_off, n, max_seg, ws,
+                                                             opts=opts))
+    ref = out.clone()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            hv.hvms_segmented_sort_i32(k, out, d_off, n, max_seg, ws, opts=opts)
+    torch.cuda.current_stream().wait_stream(s)
+    graph_ms = _median_ms(g.replay)
+    graph_ok = bool(torch.equal(out, ref))
+    # plain sort per array, same inputs, one ABI call each (workspace sized once)
+    ws2 = hv._workspace(hv.lib().hvms_sort_workspace_bytes(max_seg, 0, None), dev)
+    L = hv.lib()
+    st = hv._stream(None)
+    kp, op = k.data_ptr(), out.data_ptr()
+    wp, wb = (ws2.data_ptr(), ws2.numel()) if ws2 is not None else (None, 0)
+    offl = offs.tolist()
+
+    def per_array():
+        for i in range(len(offl) - 1):
+            m = offl[i + 1] - offl[i]
+            if m:
+                L.hvms_sort_i32(hv._vp(kp + 4 * offl[i]), hv._vp(op + 4 * offl[i]), m,
+                                hv._vp(wp), wb, st, None)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    per_array()
+    b.record()
+    torch.cuda.synchronize()
+    per_ms = a.elapsed_time(b)
+    per_ok = bool(torch.equal(out, ref))
+    return {"keys": n, "segments": int(sizes.numel()), "options": opts,
+            "batched_ms": round(eager_ms, 3), "batched_gkeys_per_s": round(n / eager_ms / 1e6, 2),
+            "graph_ms": round(graph_ms, 3), "graph_gkeys_per_s": round(n / graph_ms / 1e6, 2),
+            "per_array_plain_sort_ms": round(per_ms, 1),
+            "per_array_gkeys_per_s": round(n / per_ms / 1e6, 3),
+            "graph_replay_equal": graph_ok, "per_array_equal": per_ok}
+
+
+def learned_bench():
+    """2^30 keys from the 8-Gaussian + lognormal mixture: co-rank modes."""
+    dev = torch.device("cuda", 0)
+    n = 1 << 30
+    x = inputs.keys(n, "mixture", seed=0, device=dev)
+    out = torch.empty_like(x)
+    from paper_2409_03970_amd import tune
+    opts = tune.tuned_options("sort", n) or {}
+    ws = hv._workspace(hv.lib().hvms_sort_workspace_bytes(n, 0, hv._opts(opts)), dev)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    params = hv.fit_cdf_model(x, frac=0.01, steps=400, batch=65536, lr=3e-3, seed=2)
+    t1.record()
+    torch.cuda.synchronize()
+    res = {"n": n, "train_ms_incl_sample_sort": round(t0.elapsed_time(t1), 2)}
+    for name, mode in (("binary", hv.CORANK_BINARY), ("learned", hv.CORANK_LEARNED),
+                       ("linear", hv.CORANK_LINEAR)):
+        res[name] = _mode_stats(x, out, ws, opts, params, mode, radius=13)
+    o = out[:: 1 << 10]
+    res["sorted_ok"] = bool((out[1:] >= out[:-1]).all()) and o.numel() > 0
+    return res
+
+
+def small_bench():
+    """1,048,576 uniform keys (fits in L2 / infinity cache): launch bound."""
+    dev = torch.device("cuda", 0)
+    n = 1 << 20
+    x = inputs.keys(n, "uniform", seed=0, device=dev)
+    out = torch.empty_like(x)
+    from paper_2409_03970_amd import tune
+    opts = tune.tuned_options("sort", n) or {}
+    ws = hv._workspace(hv.lib().hvms_sort_workspace_bytes(n, 0, hv._opts(opts)), dev)
+    ms = _median_ms(lambda: hv.hvms_sort_i32(x, out, ws, opts=opts), reps=20)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            hv.hvms_sort_i32(x, out, ws, opts=opts)
+    torch.cuda.current_stream().wait_stream(s)
+    gms = _median_ms(g.replay, reps=20)
+    return {"ms": round(ms, 4), "gkeys_per_s": round(n / ms / 1e6, 2), "graph_ms": round(gms, 4),
+            "graph_gkeys_per_s": round(n / gms / 1e6, 2), "options": opts}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +246,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="sort_2p28_six", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--keys-per-lane", type=int, default=0)
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--merge-tile", type=int, default=0)
@@ -88,10 +263,14 @@ def main():
     torch.cuda.set_device(dev)
     opts = {"keys_per_lane": args.keys_per_lane, "block_threads": args.block_threads,
             "merge_tile": args.merge_tile, "wave_levels": args.wave_levels}
+    if not any(opts.values()):
+        from paper_2409_03970_amd import tune
+        opts = tune.tuned_options("sort", n) or opts
+    opts = {k: int(v) for k, v in opts.items()}
     o_probe = hv._opts(opts)
     ws_bytes = hv.lib().hvms_sort_workspace_bytes(n, 0, o_probe)
-    R = args.keys_per_lane or 16
-    NT = args.block_threads or 512
+    R = opts.get("keys_per_lane") or 16
+    NT = opts.get("block_threads") or 512
     tile = R * NT
     passes = max(0, int(np.ceil(np.log2(max(1, -(-n // tile))))))
 
@@ -169,7 +348,9 @@ def main():
         "config": {
             "workload": f"sort of 2^{log2n} int32 keys, each of: {', '.join(dists)}",
             "n": n, "distributions": list(dists), "keys_per_lane": R, "block_threads": NT,
-            "block_tile": tile, "merge_tile": args.merge_tile or 8192, "merge_passes": passes,
+            "block_tile": tile, "merge_tile": opts.get("merge_tile") or min(8192, 2 * tile),
+            "wave_levels": (opts.get("wave_levels") or 7) - 1,
+            "merge_variant": opts.get("merge_variant") or 2, "merge_passes": passes,
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -183,6 +364,25 @@ def main():
         "gkeys_per_s_by_distribution": per_dist,
         "wall_s_timed": wall,
     }
+    if not args.quick:
+        log("corank_modes_2p28")
+        try:
+            rec["corank_modes_2p28"] = corank_modes(xs, dists, out, ws, opts)
+        except Exception as e:  # an extra must never cost the headline line
+            rec["corank_modes_2p28"] = {"error": repr(e)}
+        del xs, out, ws, ev_sets
+        torch.cuda.empty_cache()
+        extras = (("pairs_2p28", lambda: pairs_bench(n)),
+                  ("batched_200k_segments", batched_bench),
+                  ("learned_2p30_mixture", learned_bench),
+                  ("small_2p20", small_bench))
+        for name, fn in extras:
+            log(name)
+            try:
+                rec[name] = fn()
+            except Exception as e:  # an extra must never cost the headline line
+                rec[name] = {"error": repr(e)}
+            torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(dists, log2n)

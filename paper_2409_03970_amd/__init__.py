@@ -256,8 +256,17 @@ def hvms_cdf_sample_i32(keys, m, seed, out, stream=None):
 
 # -------------------------------------------------- allocating conveniences
 
+def _auto(op, n, opts):
+    """Explicit options win; otherwise the autotuner's cached entry, if any."""
+    if opts is not None:
+        return opts
+    from . import tune
+    return tune.tuned_options(op, n)
+
+
 def sort(keys, out=None, opts=None, stream=None):
     """Sorted copy of an int32 device tensor (out may be keys: in place)."""
+    opts = _auto("sort", keys.numel(), opts)
     if out is None:
         out = torch.empty_like(keys)
     ws = _workspace(lib().hvms_sort_workspace_bytes(keys.numel(), 0, _opts(opts)), keys.device)
@@ -266,6 +275,7 @@ def sort(keys, out=None, opts=None, stream=None):
 
 
 def sort_pairs(keys, vals, keys_out=None, vals_out=None, opts=None, stream=None):
+    opts = _auto("sort_pairs", keys.numel(), opts)
     keys_out = torch.empty_like(keys) if keys_out is None else keys_out
     vals_out = torch.empty_like(vals) if vals_out is None else vals_out
     ws = _workspace(lib().hvms_sort_workspace_bytes(keys.numel(), 1, _opts(opts)), keys.device)
@@ -295,6 +305,7 @@ def corank(a, b, diag, opts=None, stream=None):
 
 def segmented_sort(keys, offsets, max_seg=None, out=None, opts=None, stream=None):
     """offsets: int64 tensor of nseg+1 entries (host or device)."""
+    opts = _auto("segmented", keys.numel(), opts)
     out = torch.empty_like(keys) if out is None else out
     off_host = offsets.cpu()
     nseg = off_host.numel() - 1
@@ -309,6 +320,7 @@ def segmented_sort(keys, offsets, max_seg=None, out=None, opts=None, stream=None
 
 
 def segmented_sort_pairs(keys, vals, offsets, max_seg=None, opts=None, stream=None):
+    opts = _auto("segmented_pairs", keys.numel(), opts)
     ko, vo = torch.empty_like(keys), torch.empty_like(vals)
     off_host = offsets.cpu()
     nseg = off_host.numel() - 1

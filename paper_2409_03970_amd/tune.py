@@ -1,0 +1,171 @@
+"""Autotuner for the sort's tile shapes.
+
+Searches keys per lane (R), block-sort threads, cross-lane merge levels, the
+merge tile and the merge kernel variant for one operation and size bucket,
+timing every candidate with HIP events through the C ABI.  A candidate
+counts only if its output is bit-identical to the default configuration's
+output on the same input (the default itself is checked against the CPU
+oracle by the test suite).  Winners are cached in JSON, keyed by
+(architecture, CU count, operation, log2 size bucket):
+
+    python -m paper_2409_03970_amd.tune --op sort --log2n 28
+    python -m paper_2409_03970_amd.tune --op segmented --nseg 200000
+
+The library itself never reads the cache; the allocating conveniences of the
+Python binding (sort, sort_pairs, segmented_sort) use a cached entry when
+they are called without explicit options.
+"""
+import argparse
+import itertools
+import json
+import math
+import os
+import statistics
+import sys
+
+import torch
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def _key(op, log2n):
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(props, "gcnArchName", "gfx").split(":")[0]
+    return f"{arch}:{props.multi_processor_count}:{op}:{int(log2n)}"
+
+
+def load_cache(path=CACHE):
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def tuned_options(op, n, path=CACHE):
+    """Cached options for (op, nearest size bucket) on this device, or None."""
+    if not torch.cuda.is_available() or n <= 0:
+        return None
+    cache = load_cache(path)
+    if not cache:
+        return None
+    log2n = max(0, int(round(math.log2(n))))
+    best = None
+    for k, v in cache.items():
+        parts = k.split(":")
+        if len(parts) != 4 or ":".join(parts[:3]) != _key(op, 0).rsplit(":", 1)[0]:
+            continue
+        d = abs(int(parts[3]) - log2n)
+        if d <= 2 and (best is None or d < best[0]):
+            best = (d, v["options"])
+    return dict(best[1]) if best else None
+
+
+def candidates(op):
+    shapes = [(16, 256), (16, 512), (16, 1024), (8, 1024), (32, 256), (32, 512)]
+    if op == "sort":
+        shapes.append((32, 1024))
+    out = []
+    for (R, NT), K, TM, V in itertools.product(shapes, (6, 5, 4), (4096, 8192), (2, 3)):
+        if TM > 2 * R * NT:
+            continue
+        if op != "sort" and R * NT * 8 > 163840:
+            continue
+        out.append(dict(keys_per_lane=R, block_threads=NT, wave_levels=K + 1, merge_tile=TM,
+                        merge_variant=V))
+    return out
+
+
+def _time(fn, reps):
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return statistics.median(ts)
+
+
+def tune(op="sort", log2n=24, nseg=200000, seg_max=65536, reps=5, seed=0, path=CACHE,
+         cands=None, verbose=True):
+    import paper_2409_03970_amd as hv
+    from paper_2409_03970_amd import inputs
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if op == "segmented":
+        sizes = inputs.log_uniform_sizes(nseg, 1, seg_max, seed=seed)
+        offs = inputs.offsets_from_sizes(sizes)
+        n = int(offs[-1])
+        d_off = offs.to(dev)
+        max_seg = int(sizes.max())
+        keys = inputs.keys(n, "uniform", seed=seed, device=dev)
+        out = torch.empty_like(keys)
+
+        def run(o):
+            ws = hv._workspace(hv.lib().hvms_segmented_workspace_bytes(
+                n, nseg, max_seg, 0, hv._opts(o)), dev)
+            return lambda: hv.hvms_segmented_sort_i32(keys, out, d_off, n, max_seg, ws, opts=o)
+        log2n = int(round(math.log2(n)))
+        outputs = (out,)
+    elif op in ("sort", "sort_pairs"):
+        n = 1 << log2n
+        keys = inputs.keys(n, "uniform", seed=seed, device=dev)
+        vals = torch.arange(n, device=dev, dtype=torch.int32)
+        out = torch.empty_like(keys)
+        vout = torch.empty_like(vals)
+
+        def run(o):
+            pairs = op == "sort_pairs"
+            ws = hv._workspace(hv.lib().hvms_sort_workspace_bytes(n, int(pairs), hv._opts(o)), dev)
+            if pairs:
+                return lambda: hv.hvms_sort_pairs_i32(keys, vals, out, vout, ws, opts=o)
+            return lambda: hv.hvms_sort_i32(keys, out, ws, opts=o)
+        outputs = (out, vout) if op == "sort_pairs" else (out,)
+    else:
+        raise ValueError(op)
+
+    default = {}
+    f = run(default)
+    f()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in outputs]
+    base_ms = _time(f, reps)
+    results = [(base_ms, default)]
+    for o in (cands or candidates(op)):
+        f = run(o)
+        f()
+        torch.cuda.synchronize()
+        if not all(torch.equal(a, b) for a, b in zip(outputs, ref)):
+            raise RuntimeError(f"candidate {o} changed the output")
+        ms = _time(f, reps)
+        results.append((ms, o))
+        if verbose:
+            print(f"  {ms:8.3f} ms  {o}", flush=True)
+    results.sort(key=lambda r: r[0])
+    best_ms, best = results[0]
+    cache = load_cache(path)
+    cache[_key(op, log2n)] = {"options": best, "ms": best_ms, "default_ms": base_ms, "n": n,
+                              "candidates": len(results)}
+    with open(path, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    if verbose:
+        print(f"{op} 2^{log2n}: best {best_ms:.3f} ms {best} (default {base_ms:.3f} ms)",
+              flush=True)
+    return best, best_ms, base_ms
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--op", default="sort", choices=["sort", "sort_pairs", "segmented"])
+    ap.add_argument("--log2n", type=int, default=24)
+    ap.add_argument("--nseg", type=int, default=200000)
+    ap.add_argument("--seg-max", type=int, default=65536)
+    ap.add_argument("--reps", type=int, default=5)
+    a = ap.parse_args()
+    tune(a.op, a.log2n, a.nseg, a.seg_max, a.reps)
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    main()
