@@ -324,6 +324,8 @@ static int run_segmented(const int32_t *kin, const int32_t *vin, int32_t *kout, 
     int st = resolve(opt, pairs, c);
     if (st)
         return st;
+    if (!segmented_supported(c.R, c.NT, pairs))
+        return HVMS_ERR_UNSUPPORTED;
     if (nseg == 0 || n_total == 0)
         return HVMS_OK;
     // the merge passes move 16-byte chunks of the output and scratch arrays

@@ -27,7 +27,8 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
                                                         bool blocked)
 {
     constexpr int TILE = R * NT;
-    __shared__ T S[TILE];
+    __shared__ __attribute__((aligned(16))) T S[LdsSkew<T>::size(TILE)];
+    const LdsSkew<T> Z{S, 0};
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
@@ -42,10 +43,10 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int64_t g = tile0 + t + NT * j;
-            S[t + NT * j] = g < n ? load_elem<T>(kin, vin, g) : Traits<T>::kMax;
+            Z[t + NT * j] = g < n ? load_elem<T>(kin, vin, g) : Traits<T>::kMax;
         }
         __syncthreads();
-        const T *W = S + wave * (64 * R) + lane * R;
+        const LdsSkew<T> W{S, wave * (64 * R) + lane * R};
 #pragma unroll
         for (int r = 0; r < R; ++r)
             v[r] = W[r];
@@ -67,13 +68,13 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
     if (tile0 + TILE <= n) {
 #pragma unroll
         for (int j = 0; j < R; ++j)
-            store_elem<T>(kout, vout, tile0 + t + NT * j, S[t + NT * j]);
+            store_elem<T>(kout, vout, tile0 + t + NT * j, Z[t + NT * j]);
     } else {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int64_t g = tile0 + t + NT * j;
             if (g < n)
-                store_elem<T>(kout, vout, g, S[t + NT * j]);
+                store_elem<T>(kout, vout, g, Z[t + NT * j]);
         }
     }
 }
@@ -93,7 +94,8 @@ bool block_sort_supported(int R, int NT, bool pairs)
 {
     const bool r_ok = R == 8 || R == 16 || R == 32;
     const bool nt_ok = NT == 256 || NT == 512 || NT == 1024;
-    const long lds = (long)R * NT * (pairs ? 8 : 4);
+    const long tile = (long)R * NT;
+    const long lds = pairs ? LdsSkew<int64_t>::size(tile) * 8 : LdsSkew<int32_t>::size(tile) * 4;
     return r_ok && nt_ok && lds <= 163840;
 }
 

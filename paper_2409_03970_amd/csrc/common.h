@@ -80,8 +80,14 @@ template <typename T> __device__ __forceinline__ void cmpx(T &a, T &b)
 // and its partner's (upper == false) or the max (upper == true).
 template <typename T> __device__ __forceinline__ T keep(T v, T p, bool upper)
 {
-    const bool s = p < v;
-    return (s != upper) ? p : v;
+    if constexpr (sizeof(T) == 4) {
+        const T mn = v < p ? v : p;
+        const T mx = v < p ? p : v;
+        return upper ? mx : mn;
+    } else {
+        const bool s = p < v;
+        return (s != upper) ? p : v;
+    }
 }
 
 // ------------------------------------------------------------ lane exchange
@@ -97,20 +103,22 @@ __device__ __forceinline__ int lane_id()
 // the partners across the two 32-lane halves.
 template <int M> __device__ __forceinline__ int32_t xlane32(int32_t v)
 {
+    // update_dpp with every row and bank enabled and bound_ctrl set, so the
+    // compiler can fold the exchange into the consuming v_min / v_max
     if constexpr (M == 1)
-        return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+        return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);  // quad_perm 1,0,3,2
     else if constexpr (M == 2)
-        return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+        return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);  // quad_perm 2,3,0,1
     else if constexpr (M == 3)
-        return __builtin_amdgcn_mov_dpp(v, 0x1B, 0xF, 0xF, false);  // quad_perm 3,2,1,0
+        return __builtin_amdgcn_update_dpp(0, v, 0x1B, 0xF, 0xF, true);  // quad_perm 3,2,1,0
     else if constexpr (M == 4)
-        return __builtin_amdgcn_ds_swizzle(v, 0x101F);              // xor 4
+        return __builtin_amdgcn_ds_swizzle(v, 0x101F);                    // xor 4
     else if constexpr (M == 7)
-        return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false); // row_half_mirror
+        return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true); // row_half_mirror
     else if constexpr (M == 8)
-        return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false); // row_ror:8
+        return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, true); // row_ror:8
     else if constexpr (M == 15)
-        return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false); // row_mirror
+        return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true); // row_mirror
     else if constexpr (M == 16)
         return __builtin_amdgcn_ds_swizzle(v, 0x401F);              // xor 16
     else if constexpr (M == 31)
@@ -218,11 +226,31 @@ template <int R, typename T> __device__ __forceinline__ void wave_merge(T (&v)[R
 
 // ------------------------------------------------------- merge path (a4-a6)
 
-// Co-rank of diagonal d in the merge of S[0..alen) and S[boff..boff+blen)
-// (LDS): the number of elements taken from the first run among the first d
-// outputs of the merge that takes the first run on ties.
-template <typename T>
-__device__ __forceinline__ int lds_corank(const T *S, int alen, int boff, int blen, int d)
+// LDS views.  LdsPlain indexes an array directly.  LdsSkew inserts 16 bytes
+// after every 16 elements, so that lanes writing or reading R consecutive
+// elements each (stride R elements) hit distinct banks: with R = 16 int32
+// the lane stride becomes 80 bytes and the 16 lanes of one ds_write_b128
+// pass cover all 64 banks once.
+template <typename T> struct LdsPlain {
+    T *S;
+    int base;
+    __device__ __forceinline__ T &operator[](int i) const { return S[base + i]; }
+    static constexpr int size(int n) { return n; }
+};
+template <typename T> struct LdsSkew {
+    T *S;
+    int base;
+    static constexpr int kPad = 16 / (int)sizeof(T);
+    __device__ __forceinline__ static int pos(int i) { return i + (i >> 4) * kPad; }
+    __device__ __forceinline__ T &operator[](int i) const { return S[pos(base + i)]; }
+    static constexpr int size(int n) { return n + (n / 16) * kPad; }
+};
+
+// Co-rank of diagonal d in the merge of S[0..alen) and S[boff..boff+blen):
+// the number of elements taken from the first run among the first d outputs
+// of the merge that takes the first run on ties.
+template <typename V>
+__device__ __forceinline__ int lds_corank(const V &S, int alen, int boff, int blen, int d)
 {
     int lo = d > blen ? d - blen : 0;
     int hi = d < alen ? d : alen;
@@ -238,8 +266,8 @@ __device__ __forceinline__ int lds_corank(const T *S, int alen, int boff, int bl
 
 // Serial merge of VT outputs starting at positions (i, j) of the two runs in
 // S (first run at 0, second at boff); one LDS read per output.
-template <int VT, typename T>
-__device__ __forceinline__ void serial_merge(const T *S, int alen, int boff, int blen, int i, int j,
+template <int VT, typename V, typename T>
+__device__ __forceinline__ void serial_merge(const V &S, int alen, int boff, int blen, int i, int j,
                                              T (&out)[VT])
 {
     T a = S[i < alen ? i : (alen > 0 ? alen - 1 : 0)];
@@ -262,8 +290,9 @@ __device__ __forceinline__ void serial_merge(const T *S, int alen, int boff, int
 // Steps a2-a4 on one tile: v holds each lane's R values (for runs shorter
 // than the tile: elements R*lane .. R*lane+R-1 of its wave's slice); sorts
 // the columns, runs `wave_levels` cross-lane merge levels, writes the runs to
-// S in order and merges them `lds_levels` more times in LDS.  On return (after
-// a barrier) S[p] is element p of the tile's sorted runs.
+// the skewed LDS tile in order and merges them `lds_levels` more times in
+// LDS.  On return (after a barrier) element p of the tile's sorted runs is at
+// LdsSkew position p of S.
 template <int R, int NT, typename T>
 __device__ __forceinline__ void sort_tile_core(T *S, T (&v)[R], int t, int wave_levels,
                                                int lds_levels)
@@ -273,7 +302,7 @@ __device__ __forceinline__ void sort_tile_core(T *S, T (&v)[R], int t, int wave_
     column_sort<R>(v);
     wave_merge<R>(v, lane, wave_levels);
 
-    T *W = S + wave * (64 * R) + lane * R;
+    const LdsSkew<T> W{S, wave * (64 * R) + lane * R};
 #pragma unroll
     for (int r = 0; r < R; ++r)
         W[r] = v[r];
@@ -284,14 +313,15 @@ __device__ __forceinline__ void sort_tile_core(T *S, T (&v)[R], int t, int wave_
         const int o0 = t * R;
         const int base = o0 & ~(2 * run - 1);
         const int d = o0 - base;
-        const T *P = S + base;
+        const LdsSkew<T> P{S, base};
         const int i = lds_corank(P, run, run, run, d);
         T out[R];
         serial_merge<R>(P, run, run, run, i, d - i, out);
         __syncthreads();
+        const LdsSkew<T> O{S, o0};
 #pragma unroll
         for (int k = 0; k < R; ++k)
-            S[o0 + k] = out[k];
+            O[k] = out[k];
         __syncthreads();
     }
 }

@@ -62,6 +62,7 @@ struct SegArgs {
     CorankOpts co;
     void *ws;
 };
+bool segmented_supported(int R, int NT, bool pairs);
 hipError_t launch_segmented(const SegArgs &a, hipStream_t s);
 
 }  // namespace hvms

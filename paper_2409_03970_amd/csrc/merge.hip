@@ -89,9 +89,10 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(const int32_t *__restric
     __syncthreads();
 
     const int diag = t * VT < cnt ? t * VT : cnt;
-    const int i = lds_corank(S, acnt, acnt, bcnt, diag);
+    const LdsPlain<T> SV{S, 0};
+    const int i = lds_corank(SV, acnt, acnt, bcnt, diag);
     T out[VT];
-    serial_merge<VT>(S, acnt, acnt, bcnt, i, diag - i, out);
+    serial_merge<VT>(SV, acnt, acnt, bcnt, i, diag - i, out);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < VT; ++k)

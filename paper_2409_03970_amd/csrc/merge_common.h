@@ -440,7 +440,7 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
             crn = gn + step < last ? load_cr(gn + step) : 0;
         }
 
-        const T *A = S + cur.a_off;
+        const LdsPlain<T> A{S, cur.a_off};
         const int boff = cur.b_base - cur.a_off;
         const int diag = t * VT < cur.cnt ? t * VT : cur.cnt;
         const int i = lds_corank(A, cur.acnt, boff, cur.bcnt, diag);

@@ -237,7 +237,8 @@ __global__ __launch_bounds__(NT) void seg_block_kernel(SegParams P, unsigned lon
                                                        int32_t *__restrict__ sv, int wave_max)
 {
     constexpr int TILE = R * NT;
-    __shared__ T S[TILE];
+    __shared__ __attribute__((aligned(16))) T S[LdsSkew<T>::size(TILE)];
+    const LdsSkew<T> Z{S, 0};
     __shared__ int64_t s_off[NT];
     __shared__ int32_t s_len[NT], s_dst[NT];
     __shared__ unsigned long long s_ticket;
@@ -277,11 +278,11 @@ __global__ __launch_bounds__(NT) void seg_block_kernel(SegParams P, unsigned lon
             T x = Traits<T>::kMax;
             if (slot < npieces && j < s_len[slot])
                 x = load_elem<T>(ik, iv, s_off[slot] + j);
-            S[p] = x;
+            Z[p] = x;
         }
         __syncthreads();
         T v[R];
-        const T *W = S + wave * (64 * R) + lane * R;
+        const LdsSkew<T> W{S, wave * (64 * R) + lane * R};
 #pragma unroll
         for (int r = 0; r < R; ++r)
             v[r] = W[r];
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(NT) void seg_block_kernel(SegParams P, unsigned lon
             const int slot = p >> xlog, j = p & ((1 << xlog) - 1);
             if (slot < npieces && j < s_len[slot]) {
                 const bool scr = s_dst[slot] != 0;
-                store_elem<T>(scr ? sk : ok, scr ? sv : ov, s_off[slot] + j, S[p]);
+                store_elem<T>(scr ? sk : ok, scr ? sv : ov, s_off[slot] + j, Z[p]);
             }
         }
         __syncthreads();
@@ -401,7 +402,9 @@ static hipError_t launch_seg_block_any(int R, int NT, bool pairs, const SegParam
                                                          a.vout, sk, sv, a.K, s);
     HVMS_SB(16, 256)
     HVMS_SB(16, 512)
-    HVMS_SB(16, 1024)
+    if (R == 16 && NT == 1024 && !pairs)  // the pair tile plus piece table exceeds LDS
+        return launch_seg_block<16, 1024, int32_t>(P, ctrl, pieces, a.kin, a.vin, a.kout, a.vout,
+                                                   sk, sv, a.K, s);
     HVMS_SB(8, 256)
     HVMS_SB(8, 512)
     HVMS_SB(8, 1024)
@@ -409,6 +412,14 @@ static hipError_t launch_seg_block_any(int R, int NT, bool pairs, const SegParam
     HVMS_SB(32, 512)
 #undef HVMS_SB
     return hipErrorInvalidValue;
+}
+
+bool segmented_supported(int R, int NT, bool pairs)
+{
+    const long tile = (long)R * NT;
+    const long lds = (pairs ? LdsSkew<int64_t>::size(tile) * 8 : LdsSkew<int32_t>::size(tile) * 4) +
+                     (long)NT * 16 + 8;
+    return block_sort_supported(R, NT, pairs) && lds <= 163840 && !(R == 32 && NT == 1024);
 }
 
 hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
