@@ -20,7 +20,8 @@ __all__ = [
     "hvms_cdf_forward", "hvms_cdf_backward", "hvms_cdf_adam_step", "hvms_cdf_train",
     "sort", "sort_pairs", "sort_runs", "merge_pass", "corank", "segmented_sort",
     "segmented_sort_pairs", "cdf_forward", "cdf_backward", "cdf_adam_step", "cdf_train",
-    "hvms_cdf_sample_i32", "cdf_sample", "fit_cdf_model",
+    "hvms_cdf_sample_i32", "cdf_sample", "fit_cdf_model", "segmented_sort_pairs_grouped",
+    "segment_groups",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -332,6 +333,49 @@ def segmented_sort_pairs(keys, vals, offsets, max_seg=None, opts=None, stream=No
                     keys.device)
     hvms_segmented_sort_pairs_i32(keys, vals, ko, vo, d_off, n_total, max_seg, ws, stream, opts)
     return ko, vo
+
+
+def segment_groups(off_host, max_group_keys):
+    """Consecutive segment ranges [s0, s1) whose keys (from off[s0] rounded
+    down to a multiple of 4, so every group's arrays stay 16-byte aligned)
+    fit max_group_keys; a single larger segment forms its own group."""
+    groups, nseg, s0 = [], len(off_host) - 1, 0
+    while s0 < nseg:
+        base = off_host[s0] & ~3
+        s1 = s0 + 1
+        while s1 < nseg and off_host[s1 + 1] - base <= max_group_keys:
+            s1 += 1
+        groups.append((s0, s1, base))
+        s0 = s1
+    return groups
+
+
+def segmented_sort_pairs_grouped(keys, vals, offsets, max_group_keys=1 << 30, opts=None,
+                                 stream=None, opts_for_group=None):
+    """In-place segmented pair sort with bounded scratch: the segments are
+    sorted group by group (each group one batched call), so the workspace
+    holds scratch for one group instead of the whole array.  opts_for_group,
+    if given, is called as opts_for_group(keys_view, group_index) and returns
+    the options of that group's call (e.g. a CDF model trained on it)."""
+    off_host = offsets.cpu().tolist()
+    d_off = offsets.to(keys.device) if not offsets.is_cuda else offsets
+    groups = segment_groups(off_host, max_group_keys)
+    sizes = [off_host[i + 1] - off_host[i] for i in range(len(off_host) - 1)]
+    max_seg = max(sizes) if sizes else 0
+    gmax = max((off_host[s1] - base for s0, s1, base in groups), default=0)
+    smax = max((s1 - s0 for s0, s1, base in groups), default=0)
+    o0 = opts if opts is not None else {}
+    ws = _workspace(lib().hvms_segmented_workspace_bytes(gmax, smax, max_seg, 1, _opts(o0)),
+                    keys.device)
+    for gi, (s0, s1, base) in enumerate(groups):
+        n_g = off_host[s1] - base
+        kg = keys[base:base + n_g]
+        vg = vals[base:base + n_g]
+        sub = d_off[s0:s1 + 1] - base
+        og = opts_for_group(kg, gi) if opts_for_group else opts
+        hvms_segmented_sort_pairs_i32(kg, vg, kg, vg, sub, n_g, max(sizes[s0:s1]), ws,
+                                      stream, og)
+    return keys, vals
 
 
 def cdf_forward(params, x, stream=None):

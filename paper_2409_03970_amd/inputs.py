@@ -96,6 +96,26 @@ def pairs(n, dist="uniform", seed=0, device="cpu"):
     return k, v
 
 
+def segment_distributions(nseg, seed=0):
+    """A distribution index in 0..5 (into DISTRIBUTIONS) for each segment."""
+    g = _gen(_seed(6, seed, nseg), torch.device("cpu"))
+    return torch.randint(0, len(DISTRIBUTIONS), (int(nseg),), generator=g)
+
+
+def segment_pairs(sizes, dists, first_segment=0, seed=0, device="cpu"):
+    """Keys and payloads of consecutive segments: segment s (numbered from
+    first_segment) draws sizes[i] keys of DISTRIBUTIONS[dists[i]] from its own
+    seed; its payload is the index within the segment."""
+    ks, vs = [], []
+    for i, (m, d) in enumerate(zip(sizes.tolist(), dists.tolist())):
+        ks.append(keys(m, DISTRIBUTIONS[d], seed=_seed(5, seed, first_segment + i), device=device))
+        vs.append(torch.arange(m, dtype=torch.int32, device=device))
+    if not ks:
+        e = torch.empty(0, dtype=torch.int32, device=device)
+        return e, e.clone()
+    return torch.cat(ks), torch.cat(vs)
+
+
 def adversarial_keys(n, pattern, seed=0, device="cpu"):
     """Edge-case patterns: equal, two_values, extremes, organ_pipe, sawtooth, negatives."""
     n = int(n)

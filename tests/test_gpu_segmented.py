@@ -164,3 +164,73 @@ def test_full_size_200k_segments():
     for s in rng.choice(sizes.numel(), 300, replace=False).tolist() + [int(sizes.argmax())]:
         a, b = offs_np[s], offs_np[s + 1]
         assert np.array_equal(ys[a:b], oracle.sort(ks[a:b])), s
+
+
+def test_grouped_pairs_match_oracle():
+    sizes = inputs.log_uniform_sizes(300, 1, 60000, seed=11)
+    dists = inputs.segment_distributions(300, seed=11)
+    offs = inputs.offsets_from_sizes(sizes)
+    k, v = inputs.segment_pairs(sizes, dists, 0, seed=11, device=DEV)
+    ek, ev = oracle.segmented_sort_pairs(k.cpu().numpy(), v.cpu().numpy(), offs.numpy())
+    hv.segmented_sort_pairs_grouped(k, v, offs, max_group_keys=200000)
+    assert np.array_equal(k.cpu().numpy(), ek) and np.array_equal(v.cpu().numpy(), ev)
+
+
+def _certify_pairs(k_in, k, v, offs_local, sizes):
+    """Output equals the oracle's iff: pairs strictly increase inside every
+    segment, payloads are a permutation of 0..size-1 per segment, and every
+    payload still points at its original key."""
+    n = k.numel()
+    d_sizes = sizes.to(DEV)
+    base = torch.repeat_interleave(offs_local[:-1].to(DEV), d_sizes)
+    assert bool(((v >= 0) & (v.long() < torch.repeat_interleave(d_sizes, d_sizes))).all())
+    src = base + v.long()
+    assert torch.equal(k_in[src], k)
+    mark = torch.zeros(n, dtype=torch.int32, device=DEV)
+    mark.index_add_(0, src, torch.ones(n, dtype=torch.int32, device=DEV))
+    assert bool((mark == 1).all())
+    del mark, src
+    inc = (k[1:] > k[:-1]) | ((k[1:] == k[:-1]) & (v[1:] > v[:-1]))
+    starts = torch.zeros(n, dtype=torch.bool, device=DEV)
+    starts[offs_local[:-1].to(DEV)] = True
+    assert bool((inc | starts[1:]).all())
+
+
+def test_full_size_50k_segments_learned_pairs():
+    # 50,000 segments, sizes log-uniform in [256, 4194304] (about 2.15e10
+    # pairs), each segment's keys from one of the six distributions, payload =
+    # index within the segment, learned co-rank; bounded scratch: generated,
+    # sorted and checked super-group by super-group
+    nseg = 50000
+    sizes = inputs.log_uniform_sizes(nseg, 256, 4194304, seed=0)
+    dists = inputs.segment_distributions(nseg, seed=0)
+    offs = inputs.offsets_from_sizes(sizes).tolist()
+    total, checked = 0, 0
+    rng = np.random.default_rng(0)
+
+    def learned(kg, gi):
+        p = hv.fit_cdf_model(kg, frac=0.01, steps=150, batch=32768, lr=3e-3, seed=gi)
+        return {"corank_mode": hv.CORANK_LEARNED, "cdf_params": p}
+
+    for s0, s1, _ in hv.segment_groups(offs, 1 << 31):
+        sz = sizes[s0:s1]
+        k, v = inputs.segment_pairs(sz, dists[s0:s1], s0, seed=0, device=DEV)
+        k_in = k.clone()
+        offs_local = inputs.offsets_from_sizes(sz)
+        _say("super-group", s0, s1, "pairs", k.numel())
+        hv.segmented_sort_pairs_grouped(k, v, offs_local, max_group_keys=1 << 30,
+                                        opts_for_group=learned)
+        torch.cuda.synchronize()
+        _certify_pairs(k_in, k, v, offs_local, sz)
+        for s in rng.choice(s1 - s0, 3, replace=False).tolist():
+            a, b = int(offs_local[s]), int(offs_local[s + 1])
+            if b - a <= 1 << 20:
+                ek, ev = oracle.sort_pairs(k_in[a:b].cpu().numpy(), np.arange(b - a, dtype=np.int32))
+                assert np.array_equal(k[a:b].cpu().numpy(), ek)
+                assert np.array_equal(v[a:b].cpu().numpy(), ev)
+                checked += 1
+        total += k.numel()
+        del k, v, k_in
+        torch.cuda.empty_cache()
+    assert total == offs[-1] and checked > 0
+    _say("pairs", total, "oracle-checked segments", checked)
