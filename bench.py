@@ -262,6 +262,118 @@ def small_bench():
             "graph_gkeys_per_s": round(n / gms / 1e6, 2), "options": opts}
 
 
+def config5_bench():
+    """50,000 segments, sizes log-uniform in [256, 4194304] (about 2.2e10
+    (key, index) pairs, each segment one of the six distributions), generated
+    super-group by super-group (about 2^31 pairs each, bounded scratch).
+    Times only the sort calls: batched with the learned co-rank (a model
+    trained per group, training timed apart), batched with binary co-rank,
+    and one plain pair sort per segment."""
+    dev = torch.device("cuda", 0)
+    nseg = 50000
+    sizes = inputs.log_uniform_sizes(nseg, 256, 4194304, seed=0)
+    dists = inputs.segment_distributions(nseg, seed=0)
+    offs = inputs.offsets_from_sizes(sizes).tolist()
+    t = {"learned": 0.0, "binary": 0.0, "per_segment": 0.0, "train": 0.0}
+    stats = torch.zeros(8, dtype=torch.int64, device=dev)
+    total, ok = 0, True
+    L = hv.lib()
+    for s0, s1, _ in hv.segment_groups(offs, 1 << 31):
+        sz = sizes[s0:s1]
+        k0, v0 = inputs.segment_pairs(sz, dists[s0:s1], s0, seed=0, device=dev)
+        offs_local = inputs.offsets_from_sizes(sz)
+        params = {}
+
+        def learned(kg, gi):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            p = hv.fit_cdf_model(kg, frac=0.01, steps=150, batch=32768, lr=3e-3, seed=gi)
+            b.record()
+            torch.cuda.synchronize()
+            t["train"] += a.elapsed_time(b)
+            params[gi] = p
+            return {"corank_mode": hv.CORANK_LEARNED, "cdf_params": p, "stats": stats}
+
+        res = {}
+        for mode in ("learned", "binary"):
+            k, v = k0.clone(), v0.clone()
+            torch.cuda.synchronize()
+            if mode == "learned":
+                hv.segmented_sort_pairs_grouped(k, v, offs_local, 1 << 30, opts_for_group=learned)
+                k, v = k0.clone(), v0.clone()      # first run trained the models
+                fn = (lambda kg, gi: {"corank_mode": hv.CORANK_LEARNED, "cdf_params": params[gi]})
+            else:
+                fn = None
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            hv.segmented_sort_pairs_grouped(k, v, offs_local, 1 << 30, opts_for_group=fn)
+            b.record()
+            torch.cuda.synchronize()
+            t[mode] += a.elapsed_time(b)
+            res[mode] = (k, v)
+        ok &= bool(torch.equal(res["learned"][0], res["binary"][0]))
+        ok &= bool(torch.equal(res["learned"][1], res["binary"][1]))
+        del res
+        # one plain pair sort per segment, same inputs
+        k, v = k0.clone(), v0.clone()
+        maxs = int(sz.max())
+        ws = hv._workspace(L.hvms_sort_workspace_bytes(maxs, 1, None), dev)
+        wp, wb = (ws.data_ptr(), ws.numel()) if ws is not None else (None, 0)
+        st = hv._stream(None)
+        ol = offs_local.tolist()
+        kp, vp = k.data_ptr(), v.data_ptr()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for i in range(len(ol) - 1):
+            m = ol[i + 1] - ol[i]
+            L.hvms_sort_pairs_i32(hv._vp(kp + 4 * ol[i]), hv._vp(vp + 4 * ol[i]),
+                                  hv._vp(kp + 4 * ol[i]), hv._vp(vp + 4 * ol[i]), m,
+                                  hv._vp(wp), wb, st, None)
+        b.record()
+        torch.cuda.synchronize()
+        t["per_segment"] += a.elapsed_time(b)
+        total += k0.numel()
+        del k, v, k0, v0, ws
+        torch.cuda.empty_cache()
+    c = stats.cpu().tolist()
+    return {"pairs": total, "segments": nseg, "learned_equals_binary": ok,
+            "batched_learned_ms": round(t["learned"], 1),
+            "batched_learned_gpairs_per_s": round(total / t["learned"] / 1e6, 2),
+            "batched_binary_ms": round(t["binary"], 1),
+            "batched_binary_gpairs_per_s": round(total / t["binary"] / 1e6, 2),
+            "per_segment_plain_ms": round(t["per_segment"], 1),
+            "per_segment_gpairs_per_s": round(total / t["per_segment"] / 1e6, 2),
+            "training_ms_all_groups": round(t["train"], 1),
+            "learned_probes_per_corank": round(c[1] / max(c[0], 1), 2),
+            "learned_fallback_rate": round(c[2] / max(c[0], 1), 4)}
+
+
+def table2_bench():
+    """The paper's Table 2 on the GPU: time to leave every run of X = R * 2^k
+    keys sorted (column network, then k cross-lane merge levels), for R = 8,
+    16, 32 and, at R = 16, the three column networks of Table 1 (60 / 63 /
+    80 comparators).  2^26 uniform keys per call, one wavefront per 64 * R
+    keys; G keys/s per (R, network, X)."""
+    dev = torch.device("cuda", 0)
+    n = 1 << 26
+    x = inputs.keys(n, "uniform", seed=0, device=dev)
+    out = torch.empty_like(x)
+    res = {}
+    for R, net, name in ((8, 0, "R8"), (16, 0, "R16*"), (16, 1, "R16-oddeven"),
+                         (16, 2, "R16-bitonic"), (32, 0, "R32")):
+        row = {}
+        for k in range(0, 7):
+            X = R << k
+            o = {"keys_per_lane": R, "block_threads": 256, "column_network": net}
+            ms = _median_ms(lambda: hv.hvms_sort_runs_i32(x, out, int(np.log2(X)), opts=o))
+            row[f"X={X}"] = round(n / ms / 1e6, 2)
+        res[name] = row
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +382,9 @@ def main():
     ap.add_argument("--workload", default="sort_2p28_six", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--all", action="store_true",
+                    help="also the 50,000-segment key-value batch (about 2.2e10 pairs, "
+                         "a minute or two)")
     ap.add_argument("--profile-copy", action="store_true",
                     help="also copy one input once with torch (a plain copy of known size "
                          "that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -403,11 +518,15 @@ def main():
             rec["corank_modes_2p28"] = {"error": repr(e)}
         del xs, out, ws, ev_sets
         torch.cuda.empty_cache()
-        extras = (("pairs_2p28", lambda: pairs_bench(n)),
+        extras = (("in_register_sort_table2", table2_bench),
+                  ("pairs_2p28", lambda: pairs_bench(n)),
+                  ("batched_learned_pairs_50k_segments", config5_bench if args.all else None),
                   ("batched_200k_segments", batched_bench),
                   ("learned_2p30_mixture", learned_bench),
                   ("small_2p20", small_bench))
         for name, fn in extras:
+            if fn is None:
+                continue
             log(name)
             try:
                 rec[name] = fn()

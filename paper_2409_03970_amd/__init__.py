@@ -55,6 +55,7 @@ class Options(ctypes.Structure):
         ("n_events", ctypes.c_int32),
         ("merge_variant", ctypes.c_int32),
         ("merge_occupancy", ctypes.c_int32),
+        ("column_network", ctypes.c_int32),
     ]
 
 

@@ -37,7 +37,7 @@ int ilog2_exact(int64_t x)
 int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
 struct Cfg {
-    int R, NT, K, TM, variant, occupancy;
+    int R, NT, K, TM, variant, occupancy, net;
     CorankOpts co;
     void *const *events;
     int n_events;
@@ -57,6 +57,9 @@ int resolve(const hvms_options *o, bool pairs, Cfg &c)
     c.TM = (o && o->merge_tile) ? o->merge_tile : (pairs ? 4096 : 8192);
     if (!(o && o->merge_tile) && c.TM > 2 * c.R * c.NT)
         c.TM = 2 * c.R * c.NT;
+    c.net = o ? o->column_network : 0;
+    if (c.net < 0 || c.net > 2 || (c.net != 0 && (c.R != 16 || pairs)))
+        return c.net < 0 || c.net > 2 ? HVMS_ERR_INVALID_ARG : HVMS_ERR_UNSUPPORTED;
     c.variant = o ? o->merge_variant : 0;
     c.occupancy = o ? o->merge_occupancy : 0;
     if (c.variant < 0 || c.variant > 3 || c.occupancy < 0 || c.occupancy > 32)
@@ -120,7 +123,8 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
     const int lds_levels = lanes_log2 - K;
     if (n <= tile)
         return hip_status(
-            launch_block_sort(c.R, c.NT, pairs, kin, vin, kout, vout, n, K, lds_levels, false, s));
+            launch_block_sort(c.R, c.NT, pairs, kin, vin, kout, vout, n, K, lds_levels, false, s,
+                              c.net));
 
     const SortWs w = sort_ws_layout(n, pairs, c);
     char *base = (char *)ws;
@@ -134,7 +138,8 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
     int32_t *dv = (P % 2 == 0) ? vout : sv;
     trace(c, 0, s);
     int st = hip_status(
-        launch_block_sort(c.R, c.NT, pairs, kin, vin, dk, dv, n, K, lds_levels, false, s));
+        launch_block_sort(c.R, c.NT, pairs, kin, vin, dk, dv, n, K, lds_levels, false, s,
+                          c.net));
     if (st)
         return st;
     trace(c, 1, s);
@@ -241,7 +246,7 @@ int hvms_sort_runs_i32(const int32_t *d_in, int32_t *d_out, int64_t n, int32_t r
     const int K = levels < c.K ? levels : c.K;
     const bool blocked = run_log2 < tile_log2;
     return hip_status(launch_block_sort(c.R, c.NT, false, d_in, nullptr, d_out, nullptr, n, K,
-                                        levels - K, blocked, (hipStream_t)stream));
+                                        levels - K, blocked, (hipStream_t)stream, c.net));
 }
 
 int64_t hvms_merge_workspace_bytes(int64_t n, int64_t run_len, const hvms_options *opt)

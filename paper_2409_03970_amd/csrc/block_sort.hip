@@ -18,7 +18,7 @@
 
 namespace hvms {
 
-template <int R, int NT, typename T>
+template <int R, int NT, typename T, int NET = 0>
 __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restrict__ kin,
                                                         const int32_t *__restrict__ vin,
                                                         int32_t *__restrict__ kout,
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
         }
     }
 
-    sort_tile_core<R, NT>(S, v, t, wave_levels, lds_levels);
+    sort_tile_core<R, NT, T, NET>(S, v, t, wave_levels, lds_levels);
 
     if (tile0 + TILE <= n) {
 #pragma unroll
@@ -79,13 +79,13 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
     }
 }
 
-template <int R, int NT, typename T>
+template <int R, int NT, typename T, int NET = 0>
 static hipError_t launch_bs(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
                             int64_t n, int wave_levels, int lds_levels, bool blocked,
                             hipStream_t s)
 {
     const int64_t tiles = (n + R * NT - 1) / (R * NT);
-    hipLaunchKernelGGL((block_sort_kernel<R, NT, T>), dim3((unsigned)tiles), dim3(NT), 0, s, kin,
+    hipLaunchKernelGGL((block_sort_kernel<R, NT, T, NET>), dim3((unsigned)tiles), dim3(NT), 0, s, kin,
                        vin, kout, vout, n, wave_levels, lds_levels, blocked);
     return hipGetLastError();
 }
@@ -101,8 +101,23 @@ bool block_sort_supported(int R, int NT, bool pairs)
 
 hipError_t launch_block_sort(int R, int NT, bool pairs, const int32_t *kin, const int32_t *vin,
                              int32_t *kout, int32_t *vout, int64_t n, int wave_levels,
-                             int lds_levels, bool blocked, hipStream_t s)
+                             int lds_levels, bool blocked, hipStream_t s, int net)
 {
+    if (net != 0) {  // the 16-input network ablation: keys, R = 16 only
+        if (R != 16 || pairs || (net != 1 && net != 2))
+            return hipErrorInvalidValue;
+#define HVMS_BSN(NN)                                                                               \
+    if (NT == NN)                                                                                  \
+        return net == 1 ? launch_bs<16, NN, int32_t, 1>(kin, vin, kout, vout, n, wave_levels,     \
+                                                        lds_levels, blocked, s)                   \
+                        : launch_bs<16, NN, int32_t, 2>(kin, vin, kout, vout, n, wave_levels,     \
+                                                        lds_levels, blocked, s);
+        HVMS_BSN(256)
+        HVMS_BSN(512)
+        HVMS_BSN(1024)
+#undef HVMS_BSN
+        return hipErrorInvalidValue;
+    }
 #define HVMS_BS(RR, NN)                                                                         \
     if (R == RR && NT == NN) {                                                                  \
         if (pairs)                                                                              \

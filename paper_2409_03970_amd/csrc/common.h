@@ -142,9 +142,19 @@ template <int M, typename T> __device__ __forceinline__ T xlane(T v)
 
 // Each lane sorts the R values it holds with the network table for R
 // (Sec. 2.3): 60 comparators at R = 16, Batcher's odd-even sort otherwise.
-template <int R, typename T> __device__ __forceinline__ void column_sort(T (&v)[R])
+// NET selects the 16-input alternatives of the Table 1 ablation: 1 = Batcher
+// odd-even (63 comparators), 2 = bitonic (80).
+template <int R, typename T, int NET = 0> __device__ __forceinline__ void column_sort(T (&v)[R])
 {
-    if constexpr (R == 16) {
+    if constexpr (R == 16 && NET == 1) {
+#pragma unroll
+        for (int c = 0; c < HVMS_NET16_OE_SIZE; ++c)
+            cmpx(v[HVMS_NET16_OE[2 * c]], v[HVMS_NET16_OE[2 * c + 1]]);
+    } else if constexpr (R == 16 && NET == 2) {
+#pragma unroll
+        for (int c = 0; c < HVMS_NET16_BT_SIZE; ++c)
+            cmpx(v[HVMS_NET16_BT[2 * c]], v[HVMS_NET16_BT[2 * c + 1]]);
+    } else if constexpr (R == 16) {
 #pragma unroll
         for (int c = 0; c < HVMS_NET16_SIZE; ++c)
             cmpx(v[HVMS_NET16[2 * c]], v[HVMS_NET16[2 * c + 1]]);
@@ -293,13 +303,13 @@ __device__ __forceinline__ void serial_merge(const V &S, int alen, int boff, int
 // the skewed LDS tile in order and merges them `lds_levels` more times in
 // LDS.  On return (after a barrier) element p of the tile's sorted runs is at
 // LdsSkew position p of S.
-template <int R, int NT, typename T>
+template <int R, int NT, typename T, int NET = 0>
 __device__ __forceinline__ void sort_tile_core(T *S, T (&v)[R], int t, int wave_levels,
                                                int lds_levels)
 {
     const int lane = t & 63;
     const int wave = t >> 6;
-    column_sort<R>(v);
+    column_sort<R, T, NET>(v);
     wave_merge<R>(v, lane, wave_levels);
 
     const LdsSkew<T> W{S, wave * (64 * R) + lane * R};

@@ -20,7 +20,7 @@ struct CorankOpts {
 bool block_sort_supported(int R, int NT, bool pairs);
 hipError_t launch_block_sort(int R, int NT, bool pairs, const int32_t *kin, const int32_t *vin,
                              int32_t *kout, int32_t *vout, int64_t n, int wave_levels,
-                             int lds_levels, bool blocked, hipStream_t s);
+                             int lds_levels, bool blocked, hipStream_t s, int net = 0);
 
 // merge.hip
 bool merge_tile_supported(int tm, bool pairs);

@@ -15,11 +15,36 @@
 namespace hvms {
 
 // Co-ranks of the first diagonal of every output tile of a merge pass.
+// In learned mode the 256 tiles of a block belong to at most 256 merge pairs
+// (a pair has 2*run/tm >= 1 tiles); the block first evaluates the model at
+// the four run endpoints of each of its pairs, one evaluation per thread
+// and round, so every co-rank of a pair shares them.
 template <typename T>
 __global__ __launch_bounds__(256) void pass_corank_kernel(PlainMap map, int64_t run, int64_t tm,
                                                           int64_t *__restrict__ cr, CorankCtl c)
 {
+    __shared__ float4 F[256];
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c.mode == 1) {
+        const int64_t q0 = (int64_t)blockIdx.x * blockDim.x;
+        const int64_t qlast = q0 + 255 < map.ntiles - 1 ? q0 + 255 : map.ntiles - 1;
+        const int64_t p0 = q0 * tm / (2 * run), p1 = qlast * tm / (2 * run);
+        const int np = (int)(p1 - p0 + 1);
+        for (int e = threadIdx.x; e < 4 * np; e += blockDim.x) {
+            const int64_t pb = (p0 + e / 4) * 2 * run;
+            const int64_t alen = run < map.n - pb ? run : map.n - pb;
+            const int64_t rest = map.n - pb - run;
+            const int64_t blen = rest <= 0 ? 0 : (rest < run ? rest : run);
+            const int w = e & 3;
+            int64_t idx = w == 0 ? pb : w == 1 ? pb + alen - 1 : w == 2 ? pb + run : pb + run + blen - 1;
+            if (w >= 2 && blen == 0)
+                idx = pb + alen - 1;
+            ((float *)&F[e / 4])[w] = cdf_eval(c.cdf, key_to_unit(map.ik[idx]));
+        }
+        __syncthreads();
+        c.pair_cdf = F;
+        c.pair_first = p0;
+    }
     if (q < map.ntiles)
         tile_corank<T>(map, q, run, tm, cr, c);
 }
@@ -125,6 +150,8 @@ static CorankCtl make_ctl(const CorankOpts &o)
     c.radius_log2 = o.radius_log2;
     c.cdf = o.cdf;
     c.stats = o.stats;
+    c.pair_cdf = nullptr;
+    c.pair_first = 0;
     return c;
 }
 
@@ -132,6 +159,7 @@ hipError_t launch_pass_corank(bool pairs, const int32_t *kin, const int32_t *vin
                               int64_t run, int64_t tm, int64_t *cr, const CorankOpts &o,
                               hipStream_t s)
 {
+    const CorankCtl ctl = make_ctl(o);
     PlainMap map;
     map.ik = kin;
     map.iv = pairs ? vin : nullptr;
@@ -142,10 +170,10 @@ hipError_t launch_pass_corank(bool pairs, const int32_t *kin, const int32_t *vin
     const unsigned blocks = (unsigned)((map.ntiles + 255) / 256);
     if (pairs)
         hipLaunchKernelGGL(pass_corank_kernel<int64_t>, dim3(blocks), dim3(256), 0, s, map, run,
-                           tm, cr, make_ctl(o));
+                           tm, cr, ctl);
     else
         hipLaunchKernelGGL(pass_corank_kernel<int32_t>, dim3(blocks), dim3(256), 0, s, map, run,
-                           tm, cr, make_ctl(o));
+                           tm, cr, ctl);
     return hipGetLastError();
 }
 

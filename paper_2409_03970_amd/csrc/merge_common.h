@@ -17,6 +17,11 @@ struct CorankCtl {
     int radius_log2;   // bracket half-width for the bounded search
     const float *cdf;  // model parameters (learned mode)
     unsigned long long *stats;
+    // learned mode: model values at the four run endpoints of each merge
+    // pair (F(A[0]), F(A[m-1]), F(B[0]), F(B[k-1])), indexed by pair number
+    // and shared by the pair's co-ranks; nullptr = evaluate in place
+    const float4 *pair_cdf;
+    int64_t pair_first;  // pair number of pair_cdf[0]
 };
 
 // P(i) := A[i] <= B[d-1-i]  (A-first merge takes A[i] before B[d-1-i]).  The
@@ -46,14 +51,22 @@ __device__ __forceinline__ int64_t binary_corank(FA A, FB B, int64_t d, int64_t 
 //           runs with disjoint key ranges).
 template <typename FA, typename FB>
 __device__ int64_t predict_corank(const CorankCtl &c, FA Akey, FB Bkey, int64_t m, int64_t k,
-                                  int64_t d)
+                                  int64_t d, const float4 *pre)
 {
     if (c.mode != 1 || m == 0 || k == 0)
         return (int64_t)((double)d * (double)m / (double)(m + k));
-    float fa0 = cdf_eval(c.cdf, key_to_unit(Akey(0)));
-    float fa1 = cdf_eval(c.cdf, key_to_unit(Akey(m - 1)));
-    float fb0 = cdf_eval(c.cdf, key_to_unit(Bkey(0)));
-    float fb1 = cdf_eval(c.cdf, key_to_unit(Bkey(k - 1)));
+    float fa0, fa1, fb0, fb1;
+    if (pre) {
+        fa0 = pre->x;
+        fa1 = pre->y;
+        fb0 = pre->z;
+        fb1 = pre->w;
+    } else {
+        fa0 = cdf_eval(c.cdf, key_to_unit(Akey(0)));
+        fa1 = cdf_eval(c.cdf, key_to_unit(Akey(m - 1)));
+        fb0 = cdf_eval(c.cdf, key_to_unit(Bkey(0)));
+        fb1 = cdf_eval(c.cdf, key_to_unit(Bkey(k - 1)));
+    }
     if (!(fa1 > fa0)) fa1 = fa0 + 1e-7f;
     if (!(fb1 > fb0)) fb1 = fb0 + 1e-7f;
     // total count at level u: piecewise linear, nondecreasing; find u* by
@@ -93,7 +106,7 @@ __device__ int64_t predict_corank(const CorankCtl &c, FA Akey, FB Bkey, int64_t 
 
 template <typename T, typename FA, typename FB, typename KA, typename KB>
 __device__ int64_t find_corank(const CorankCtl &c, FA A, FB B, KA Akey, KB Bkey, int64_t m,
-                               int64_t k, int64_t d)
+                               int64_t k, int64_t d, const float4 *pre = nullptr)
 {
     const int64_t lo = d > k ? d - k : 0;
     const int64_t hi = d < m ? d : m;
@@ -102,7 +115,7 @@ __device__ int64_t find_corank(const CorankCtl &c, FA A, FB B, KA Akey, KB Bkey,
     if (c.mode == 0 || hi - lo <= 2) {
         res = binary_corank<T>(A, B, d, lo, hi, probes);
     } else {
-        pred = predict_corank(c, Akey, Bkey, m, k, d);
+        pred = predict_corank(c, Akey, Bkey, m, k, d, pre);
         pred = pred < lo ? lo : (pred > hi ? hi : pred);
         const int64_t r = (int64_t)1 << c.radius_log2;
         const int64_t L = pred - r > lo ? pred - r : lo;
@@ -229,7 +242,9 @@ __device__ __forceinline__ void tile_corank(const Map &map, int64_t q, int64_t r
     auto B = [=](int64_t i) { return load_elem<T>(bk, bv, i); };
     auto Ak = [=](int64_t i) { return ak[i]; };
     auto Bk = [=](int64_t i) { return bk[i]; };
-    cr[q] = find_corank<T>(c, A, B, Ak, Bk, P.alen, P.blen, P.d0);
+    // pairs start at multiples of 2 * run from the sequence start
+    const float4 *pre = c.pair_cdf ? c.pair_cdf + (P.pb / (2 * run) - c.pair_first) : nullptr;
+    cr[q] = find_corank<T>(c, A, B, Ak, Bk, P.alen, P.blen, P.d0, pre);
 }
 
 // ------------------------------------------- persistent, pipelined merge pass

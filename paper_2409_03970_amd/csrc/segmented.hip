@@ -478,6 +478,8 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
         c.radius_log2 = a.co.radius_log2;
         c.cdf = a.co.cdf;
         c.stats = a.co.stats;
+        c.pair_cdf = nullptr;
+        c.pair_first = 0;
         const unsigned cb = (unsigned)((L.max_tiles + 255) / 256);
         if (pairs)
             hipLaunchKernelGGL(seg_corank_kernel<int64_t>, dim3(cb), dim3(256), 0, s, map, run,

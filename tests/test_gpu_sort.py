@@ -258,3 +258,22 @@ def test_full_size_2pow28(dist):
     y = hv.sort(x)
     torch.cuda.synchronize()
     _full_check(x, y)
+
+
+@pytest.mark.parametrize("net", [1, 2])
+def test_alternative_column_networks_all_01_inputs(net):
+    # the Table 1 alternatives (odd-even 63, bitonic 80) through the real kernel
+    x = _runs_from_bits(16, 16)
+    y = hv.sort_runs(x, 4, opts={"keys_per_lane": 16, "block_threads": 256, "column_network": net})
+    ones = x.view(-1, 16).sum(1)
+    want = (torch.arange(16, device=DEV)[None, :] >= (16 - ones)[:, None]).to(torch.int32)
+    assert torch.equal(y.view(-1, 16), want)
+
+
+@pytest.mark.parametrize("net", [1, 2])
+@pytest.mark.parametrize("NT", [256, 512, 1024])
+def test_alternative_column_networks_full_sort(net, NT):
+    n = 5 * 16 * NT + 777
+    x = inputs.keys(n, "gaussian", seed=net, device=DEV)
+    y = hv.sort(x, opts={"keys_per_lane": 16, "block_threads": NT, "column_network": net})
+    assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy()))

@@ -68,10 +68,23 @@ def test_wave_merge_levels_merge_all_sorted_halves(R, k):
         assert oracle.merging_network_failures01(sub, s // 2, s // 2) == 0
 
 
+def _table(text, name):
+    m = re.search(rf"{name}\[\d+\] = \{{([^}}]*)\}}", text)
+    vals = [int(x) for x in m.group(1).replace(" ", "").split(",")]
+    return list(zip(vals[::2], vals[1::2]))
+
+
 def test_header_matches_generator():
     text = open(netgen.header_path()).read()
     assert text == netgen.render_header()
     for R in (4, 8, 16, 32):
-        m = re.search(rf"HVMS_NET{R}\[\d+\] = \{{([^}}]*)\}}", text)
-        vals = [int(x) for x in m.group(1).replace(" ", "").split(",")]
-        assert list(zip(vals[::2], vals[1::2])) == netgen.column_network(R)
+        assert _table(text, f"HVMS_NET{R}") == netgen.column_network(R)
+
+
+def test_header_ablation_networks(golden_dir):
+    text = open(netgen.header_path()).read()
+    bit, oe, lo, hi = _table1(golden_dir)[16]
+    oe16, bt16 = _table(text, "HVMS_NET16_OE"), _table(text, "HVMS_NET16_BT")
+    assert len(oe16) == oe and len(bt16) == bit
+    assert oracle.network_failures01(oe16, 16) == 0
+    assert oracle.network_failures01(bt16, 16) == 0
