@@ -72,12 +72,16 @@ enum {
  *                   2 persistent with the next tile prefetched during the
  *                   merge, 3 as 2 with each XCD walking contiguous tiles.
  *   merge_occupancy workgroups per CU in the persistent grid (0 = all that fit).
+ *   merge_ways      2: two-way merge passes (one merge level per pass); 4:
+ *                   four-way passes that do two levels per trip through HBM
+ *                   (an odd level count adds one two-way pass first).
  *   column_network  16-input column network (keys, keys_per_lane 16 only):
  *                   0 the 60-comparator network, 1 Batcher odd-even (63),
  *                   2 bitonic (80) -- the comparison of Table 1 / Table 2.
  *   events/n_events optional caller-owned hipEvent_t handles for tracing: a
  *                   sort records events[0]/[1] around its block-sort kernel
  *                   and events[2+2p]/[3+2p] around the merge kernel of pass p
+ *                   (two-way passes first, then four-way passes)
  *                   (as far as n_events reaches), on the call's stream.
  */
 typedef struct hvms_options {
@@ -94,6 +98,7 @@ typedef struct hvms_options {
     int32_t merge_variant;
     int32_t merge_occupancy;
     int32_t column_network;
+    int32_t merge_ways;
 } hvms_options;
 
 enum {

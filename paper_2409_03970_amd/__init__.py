@@ -56,6 +56,7 @@ class Options(ctypes.Structure):
         ("merge_variant", ctypes.c_int32),
         ("merge_occupancy", ctypes.c_int32),
         ("column_network", ctypes.c_int32),
+        ("merge_ways", ctypes.c_int32),
     ]
 
 

@@ -37,7 +37,7 @@ int ilog2_exact(int64_t x)
 int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
 struct Cfg {
-    int R, NT, K, TM, variant, occupancy, net;
+    int R, NT, K, TM, variant, occupancy, net, ways;
     CorankOpts co;
     void *const *events;
     int n_events;
@@ -57,6 +57,9 @@ int resolve(const hvms_options *o, bool pairs, Cfg &c)
     c.TM = (o && o->merge_tile) ? o->merge_tile : (pairs ? 4096 : 8192);
     if (!(o && o->merge_tile) && c.TM > 2 * c.R * c.NT)
         c.TM = 2 * c.R * c.NT;
+    c.ways = (o && o->merge_ways) ? o->merge_ways : 2;
+    if (c.ways != 2 && c.ways != 4)
+        return HVMS_ERR_INVALID_ARG;
     c.net = o ? o->column_network : 0;
     if (c.net < 0 || c.net > 2 || (c.net != 0 && (c.R != 16 || pairs)))
         return c.net < 0 || c.net > 2 ? HVMS_ERR_INVALID_ARG : HVMS_ERR_UNSUPPORTED;
@@ -77,6 +80,8 @@ int resolve(const hvms_options *o, bool pairs, Cfg &c)
     if (c.co.mode == HVMS_CORANK_LEARNED && !c.co.cdf)
         return HVMS_ERR_INVALID_ARG;
     if (!block_sort_supported(c.R, c.NT, pairs) || !merge_tile_supported(c.TM, pairs))
+        return HVMS_ERR_UNSUPPORTED;
+    if (c.ways == 4 && !merge4_supported(c.TM, pairs))
         return HVMS_ERR_UNSUPPORTED;
     if ((int64_t)c.TM > 2 * (int64_t)c.R * c.NT)
         return HVMS_ERR_UNSUPPORTED;
@@ -99,8 +104,8 @@ SortWs sort_ws_layout(int64_t n, bool pairs, const Cfg &c)
         w.scratch_v = off;
         off += align256(n * 4);
     }
-    w.coranks = off;
-    off += align256(((n + c.TM - 1) / c.TM + 1) * 8);
+    w.coranks = off;  // one int64 per tile (two-way) or one record per tile (four-way)
+    off += align256(((n + c.TM - 1) / c.TM + 2) * (int64_t)(c.ways == 4 ? merge4_record_bytes() : 8));
     w.total = off;
     return w;
 }
@@ -133,9 +138,12 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
     int64_t *cr = (int64_t *)(base + w.coranks);
 
     const int64_t nb = (n + tile - 1) / tile;
-    const int P = ilog2_exact(nb);
-    int32_t *dk = (P % 2 == 0) ? kout : sk;
-    int32_t *dv = (P % 2 == 0) ? vout : sv;
+    const int P = ilog2_exact(nb);           // merge levels
+    const int P4 = c.ways == 4 ? P / 2 : 0;  // four-way passes (two levels each)
+    const int P2 = P - 2 * P4;               // two-way passes (first)
+    const int passes = P2 + P4;
+    int32_t *dk = (passes % 2 == 0) ? kout : sk;
+    int32_t *dv = (passes % 2 == 0) ? vout : sv;
     trace(c, 0, s);
     int st = hip_status(
         launch_block_sort(c.R, c.NT, pairs, kin, vin, dk, dv, n, K, lds_levels, false, s,
@@ -144,9 +152,21 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
         return st;
     trace(c, 1, s);
     int64_t run = tile;
-    for (int p = 0; p < P; ++p, run *= 2) {
+    for (int p = 0; p < passes; ++p) {
         int32_t *ok = (dk == kout) ? sk : kout;
         int32_t *ov = (dk == kout) ? sv : vout;
+        if (p >= P2) {
+            trace(c, 2 + 2 * p, s);
+            st = hip_status(launch_merge4_pass(c.TM, pairs, dk, dv, ok, ov, n, run, cr, c.co,
+                                               c.occupancy, s));
+            if (st)
+                return st;
+            trace(c, 3 + 2 * p, s);
+            dk = ok;
+            dv = ov;
+            run *= 4;
+            continue;
+        }
         st = hip_status(launch_pass_corank(pairs, dk, dv, n, run, c.TM, cr, c.co, s));
         if (st)
             return st;
@@ -158,6 +178,7 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
         trace(c, 3 + 2 * p, s);
         dk = ok;
         dv = ov;
+        run *= 2;
     }
     return HVMS_OK;
 }

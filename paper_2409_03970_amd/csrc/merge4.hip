@@ -1,0 +1,505 @@
+// Four-way merge pass: two merge levels per trip through HBM.
+//
+// A pass with run length L merges every group of four consecutive runs
+// A, B, C, D into one run of 4L: the output is (A merge B) merge (C merge D),
+// each merge taking its first operand on ties, i.e. the order (key, run).
+// Output tile g covers [g*TM, (g+1)*TM) of its group.  Its windows follow from
+// three co-ranks of its first diagonal d: x = number of X = A(+)B elements
+// among the first d outputs of X (+) Y (Y = C(+)D), a = co-rank of x in A(+)B,
+// c = co-rank of d - x in C(+)D.  X and Y are never stored, so every probe
+// of the outer search needs an inner co-rank; because co-ranks are monotone,
+// each inner search is confined to the current outer bracket and the total
+// depth is a decreasing series instead of a product.  The merge kernel loads
+// the four windows (TM elements together), merges A with B and C with D in
+// LDS, then the two results, and writes the tile with coalesced stores.
+#include "hvms_internal.h"
+#include "merge_common.h"
+
+namespace hvms {
+
+namespace {
+
+// One virtual run V = P (+) Q of two sorted arrays (P first on ties).
+template <typename T> struct VRun {
+    const int32_t *pk, *pv, *qk, *qv;
+    int64_t np, nq;
+    __device__ __forceinline__ T P(int64_t i) const { return load_elem<T>(pk, pv, i); }
+    __device__ __forceinline__ T Q(int64_t i) const { return load_elem<T>(qk, qv, i); }
+    __device__ __forceinline__ int64_t len() const { return np + nq; }
+
+    // co-rank of diagonal k, known to lie in [lo, hi]
+    __device__ __forceinline__ int64_t rank(int64_t k, int64_t lo, int64_t hi,
+                                            unsigned &probes) const
+    {
+        const int64_t flo = k > nq ? k - nq : 0, fhi = k < np ? k : np;
+        lo = lo < flo ? flo : (lo > fhi ? fhi : lo);
+        hi = hi > fhi ? fhi : (hi < lo ? lo : hi);
+        while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            ++probes;
+            if (Q(k - 1 - mid) < P(mid))
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        return lo;
+    }
+    // element at output k (k < len) given i = co-rank(k); fromP tells which
+    // operand it came from (then co-rank(k + 1) = i + fromP)
+    __device__ __forceinline__ T at(int64_t k, int64_t i, bool &fromP) const
+    {
+        const int64_t j = k - i;
+        fromP = i < np && (j >= nq || !(Q(j) < P(i)));
+        return fromP ? P(i) : Q(j);
+    }
+    // element at output k - 1 (k >= 1) given i = co-rank(k): the larger of
+    // the last taken elements (Q's wins ties, it is merged after P's)
+    __device__ __forceinline__ T last(int64_t k, int64_t i) const
+    {
+        const int64_t j = k - i;
+        if (i == 0)
+            return Q(j - 1);
+        if (j == 0)
+            return P(i - 1);
+        const T a = P(i - 1), b = Q(j - 1);
+        return b < a ? a : b;
+    }
+};
+
+struct Quad {
+    int64_t x, a, c;  // co-ranks of a tile's first diagonal
+};
+
+template <typename T> struct Group {
+    VRun<T> X, Y;
+    int64_t gb;  // absolute index of the group's first element
+};
+
+template <typename T>
+__device__ __forceinline__ Group<T> group_of(const int32_t *k, const int32_t *v, int64_t n,
+                                             int64_t run, int64_t gq)
+{
+    Group<T> G;
+    G.gb = gq * 4 * run;
+    int64_t len[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t s = G.gb + r * run;
+        len[r] = s >= n ? 0 : (n - s < run ? n - s : run);
+    }
+    const int32_t *vb = v ? v + G.gb : nullptr;
+    G.X.pk = k + G.gb;
+    G.X.pv = vb;
+    G.X.qk = k + G.gb + run;
+    G.X.qv = vb ? vb + run : nullptr;
+    G.X.np = len[0];
+    G.X.nq = len[1];
+    G.Y.pk = k + G.gb + 2 * run;
+    G.Y.pv = vb ? vb + 2 * run : nullptr;
+    G.Y.qk = k + G.gb + 3 * run;
+    G.Y.qv = vb ? vb + 3 * run : nullptr;
+    G.Y.np = len[2];
+    G.Y.nq = len[3];
+    return G;
+}
+
+// Outer co-rank x of diagonal d of X (+) Y with the inner co-ranks carried
+// along.  Invariants: x in [lo, hi]; aL = a(lo), aH = a(hi); cL = c(d - hi),
+// cH = c(d - lo) (a, c: co-ranks in X and Y).
+template <typename T>
+__device__ Quad quad_corank(const Group<T> &G, int64_t d, const CorankCtl &ctl,
+                            unsigned &probes, unsigned &fallback)
+{
+    const VRun<T> &X = G.X, &Y = G.Y;
+    const int64_t nx = X.len(), ny = Y.len();
+    int64_t lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
+    int64_t aL, aH, cL, cH;
+    bool bracketed = false;
+    if (ctl.mode != 0 && hi - lo > 2) {
+        // linear prediction of x and of both inner co-ranks, then an exact
+        // check of the bracket ends; outside the bracket, full search
+        const int64_t r = (int64_t)1 << ctl.radius_log2;
+        const int64_t px = (int64_t)((double)d * (double)nx / (double)(nx + ny));
+        const int64_t L = px - r > lo ? px - r : lo, H = px + r < hi ? px + r : hi;
+        auto inner = [&](const VRun<T> &V, int64_t k) {
+            const int64_t pi = V.len() ? (int64_t)((double)k * (double)V.np / (double)V.len()) : 0;
+            const int64_t flo = k > V.nq ? k - V.nq : 0, fhi = k < V.np ? k : V.np;
+            const int64_t l2 = pi - r > flo ? pi - r : flo, h2 = pi + r < fhi ? pi + r : fhi;
+            ++probes;
+            const bool okl = l2 == flo || !(V.Q(k - l2) < V.P(l2 - 1));
+            const bool okh = h2 == fhi || V.Q(k - 1 - h2) < V.P(h2);
+            if (okl && okh)
+                return V.rank(k, l2, h2, probes);
+            return V.rank(k, flo, fhi, probes);
+        };
+        const int64_t aLb = inner(X, L), aHb = inner(X, H);
+        const int64_t cLb = inner(Y, d - H), cHb = inner(Y, d - L);
+        // x >= L iff L == lo or X[L-1] <= Y[d-L];  x <= H iff H == hi or Y[d-1-H] < X[H]
+        bool f;
+        const bool okL = L == lo || !(Y.at(d - L, cHb, f) < X.last(L, aLb));
+        const bool okH = H == hi || Y.last(d - H, cLb) < X.at(H, aHb, f);
+        ++probes;
+        if (okL && okH) {
+            lo = L;
+            hi = H;
+            aL = aLb;
+            aH = aHb;
+            cL = cLb;
+            cH = cHb;
+            bracketed = true;
+        } else {
+            fallback = 1;
+        }
+    }
+    if (!bracketed) {
+        aL = X.rank(lo, 0, X.np, probes);
+        aH = X.rank(hi, 0, X.np, probes);
+        cL = Y.rank(d - hi, 0, Y.np, probes);
+        cH = Y.rank(d - lo, 0, Y.np, probes);
+    }
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        // a(mid) in [max(aL, mid - hi + aH), min(aH, mid - lo + aL)]; y = d - 1 - mid
+        // likewise between c(d - hi) and c(d - lo)
+        const int64_t am = X.rank(mid, aL > mid - hi + aH ? aL : mid - hi + aH,
+                                  aH < mid - lo + aL ? aH : mid - lo + aL, probes);
+        const int64_t y = d - 1 - mid;
+        const int64_t ym = Y.rank(y, cL > y - (d - lo) + cH ? cL : y - (d - lo) + cH,
+                                  cH < y - (d - hi) + cL ? cH : y - (d - hi) + cL, probes);
+        bool fx, fy;
+        const T xv = X.at(mid, am, fx);
+        const T yv = Y.at(y, ym, fy);
+        if (yv < xv) {  // X[mid] comes after Y[d-1-mid]: x <= mid
+            hi = mid;
+            aH = am;
+            cL = ym + (fy ? 1 : 0);
+        } else {
+            lo = mid + 1;
+            aL = am + (fx ? 1 : 0);
+            cH = ym;
+        }
+    }
+    Quad q;
+    q.x = lo;
+    q.a = aL;
+    q.c = cH;
+    return q;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void quad_corank_kernel(const int32_t *__restrict__ kin,
+                                                          const int32_t *__restrict__ vin,
+                                                          int64_t n, int64_t run, int64_t tm,
+                                                          int64_t ntiles, Quad *__restrict__ out,
+                                                          CorankCtl ctl)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ntiles)
+        return;
+    const int64_t o0 = g * tm;
+    const int64_t gq = o0 / (4 * run);
+    const Group<T> G = group_of<T>(kin, vin, n, run, gq);
+    const int64_t d = o0 - G.gb;
+    unsigned probes = 0, fallback = 0;
+    out[g] = quad_corank<T>(G, d, ctl, probes, fallback);
+    if (ctl.stats) {
+        atomicAdd(ctl.stats + 0, 1ull);
+        atomicAdd(ctl.stats + 1, (unsigned long long)probes);
+        if (ctl.mode != 0)
+            atomicAdd(ctl.stats + 2, (unsigned long long)fallback);
+    }
+}
+
+struct Tile4 {
+    int64_t gb, o0;       // group start (absolute), first output (group-relative)
+    int64_t al[4];        // absolute index of the first chunk of each window
+    int cnt, nx;          // outputs; of them from X = A (+) B
+    int len[4], off[4];   // window lengths, offset of window start in its first chunk
+    int nch[4], base[4];  // chunks per window, LDS index of window element 0
+    int shift;            // (absolute first output) % 4
+};
+
+// Window geometry of tile g from the co-ranks of its first and next
+// diagonals, clamped so that every window stays inside its run and the four
+// lengths add up to the tile even if the runs were not sorted.
+template <typename T>
+__device__ __forceinline__ Tile4 tile4_geo(const Group<T> &G, int64_t run, int64_t tm, int64_t g,
+                                           Quad q0, Quad q1)
+{
+    Tile4 t;
+    const int64_t nA = G.X.np, nB = G.X.nq, nC = G.Y.np, nD = G.Y.nq;
+    const int64_t nx = nA + nB, ny = nC + nD;
+    t.gb = G.gb;
+    t.o0 = g * tm - G.gb;
+    const int64_t d0 = t.o0;
+    const int64_t d1 = d0 + tm < nx + ny ? d0 + tm : nx + ny;
+    if (d1 == nx + ny) {
+        q1.x = nx;
+        q1.a = nA;
+        q1.c = nC;
+    }
+    auto cl = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
+    const int64_t x0 = cl(q0.x, d0 > ny ? d0 - ny : 0, d0 < nx ? d0 : nx);
+    int64_t x1 = cl(q1.x, d1 > ny ? d1 - ny : 0, d1 < nx ? d1 : nx);
+    x1 = cl(x1, x0, x0 + (d1 - d0));
+    const int64_t a0 = cl(q0.a, x0 > nB ? x0 - nB : 0, x0 < nA ? x0 : nA);
+    int64_t a1 = cl(q1.a, x1 > nB ? x1 - nB : 0, x1 < nA ? x1 : nA);
+    a1 = cl(a1, a0, a0 + (x1 - x0));
+    const int64_t y0 = d0 - x0, y1 = d1 - x1;
+    const int64_t c0 = cl(q0.c, y0 > nD ? y0 - nD : 0, y0 < nC ? y0 : nC);
+    int64_t c1 = cl(q1.c, y1 > nD ? y1 - nD : 0, y1 < nC ? y1 : nC);
+    c1 = cl(c1, c0, c0 + (y1 - y0));
+    const int64_t start[4] = {G.gb + a0, G.gb + run + (x0 - a0), G.gb + 2 * run + c0,
+                              G.gb + 3 * run + (y0 - c0)};
+    const int64_t len[4] = {a1 - a0, (x1 - a1) - (x0 - a0), c1 - c0, (y1 - c1) - (y0 - c0)};
+    t.cnt = (int)(d1 - d0);
+    t.nx = (int)(x1 - x0);
+    int chunks = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        t.al[r] = start[r] & ~(int64_t)3;
+        t.off[r] = (int)(start[r] - t.al[r]);
+        t.len[r] = (int)len[r];
+        t.nch[r] = len[r] ? (t.off[r] + t.len[r] + 3) >> 2 : 0;
+        t.base[r] = 4 * chunks + t.off[r];
+        chunks += t.nch[r];
+    }
+    t.shift = (int)((G.gb + t.o0) & 3);
+    return t;
+}
+
+template <int NT, int VT, typename T>
+__global__ __launch_bounds__(NT) void merge4_pipe_kernel(const int32_t *__restrict__ kin,
+                                                         const int32_t *__restrict__ vin,
+                                                         int32_t *__restrict__ kout,
+                                                         int32_t *__restrict__ vout, int64_t n,
+                                                         int64_t run, const Quad *__restrict__ rec,
+                                                         int64_t ntiles)
+{
+    constexpr int TM = NT * VT;
+    constexpr int CH = VT / 4 + 1;  // chunk slots per thread: TM/4 + 6 chunks at most
+    __shared__ __attribute__((aligned(16))) T S[TM + 32];
+    __shared__ __attribute__((aligned(16))) T M[TM + VT];
+    const int t = threadIdx.x;
+    const int64_t first = blockIdx.x, step = gridDim.x, last = ntiles;
+    if (first >= last)
+        return;
+
+    // records of tile g and g + 1: six int64 words, one per lane 0..5
+    const int64_t *words = (const int64_t *)rec;
+    auto load_rec = [&](int64_t g) -> int64_t {
+        const int l = t & 7;
+        const int64_t gi = g + (l >= 3 ? 1 : 0);
+        const int64_t w = (gi < ntiles ? gi : ntiles - 1) * 3 + (l % 3);
+        return words[w];
+    };
+    auto rd = [](int64_t v, int lane) {
+        return (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane) |
+               ((int64_t)__builtin_amdgcn_readlane((int)(v >> 32), lane) << 32);
+    };
+    auto geo_of = [&](int64_t g, int64_t rv) {
+        Quad q0, q1;
+        q0.x = rd(rv, 0);
+        q0.a = rd(rv, 1);
+        q0.c = rd(rv, 2);
+        q1.x = rd(rv, 3);
+        q1.a = rd(rv, 4);
+        q1.c = rd(rv, 5);
+        const Group<T> G = group_of<T>(kin, vin, n, run, (g * TM) / (4 * run));
+        return tile4_geo<T>(G, run, TM, g, q0, q1);
+    };
+
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int64_t e_tail = n & ~(int64_t)3;
+    const bool has_tail = (n & 3) != 0;
+    auto chunk_elem = [&](const Tile4 &G, int c) -> int64_t {
+        const int c1 = G.nch[0], c2 = c1 + G.nch[1], c3 = c2 + G.nch[2];
+        return c < c1   ? G.al[0] + 4 * c
+               : c < c2 ? G.al[1] + 4 * (c - c1)
+               : c < c3 ? G.al[2] + 4 * (c - c2)
+                        : G.al[3] + 4 * (c - c3);
+    };
+    auto total_chunks = [](const Tile4 &G) { return G.nch[0] + G.nch[1] + G.nch[2] + G.nch[3]; };
+    Chunk<T> pf[CH];
+    auto prefetch = [&](const Tile4 &G) {
+        const int nc = total_chunks(G);
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            if (NT * q + 64 * wave < nc) {
+                const int c = t + NT * q;
+                int64_t e = c < nc ? chunk_elem(G, c) : 0;
+                e = (has_tail && e == e_tail) ? e_tail - 4 : e;
+                pf[q] = load_chunk<T>(kin, vin, e);
+            }
+        }
+    };
+
+    int64_t g = first;
+    Tile4 cur = geo_of(g, load_rec(g));
+    prefetch(cur);
+    int64_t rn = g + step < last ? load_rec(g + step) : 0;
+
+    for (;;) {
+        lds_barrier();
+        const int nc = total_chunks(cur);
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int c = t + NT * q;
+            if (c < nc) {
+                if (has_tail && chunk_elem(cur, c) == e_tail)
+                    fix_tail<T>(pf[q], kin, vin, e_tail, n);
+                put_chunk<T>(S, c, pf[q]);
+            }
+        }
+        lds_barrier();
+
+        const int64_t gn = g + step;
+        const bool more = gn < last;
+        Tile4 nxt;
+        if (more) {
+            nxt = geo_of(gn, rn);
+            prefetch(nxt);
+            rn = gn + step < last ? load_rec(gn + step) : 0;
+        }
+
+        // level 1: X = A (+) B into M[0, nx), Y = C (+) D into M[XP, XP + ny)
+        const int nxw = cur.nx, nyw = cur.cnt - cur.nx;
+        const int XP = (nxw + VT - 1) / VT * VT;
+        const int nslots = XP / VT + (nyw + VT - 1) / VT;
+        for (int s = t; s < nslots; s += NT) {
+            const bool isx = s * VT < XP;
+            const int diag = isx ? s * VT : s * VT - XP;
+            const int alen = isx ? cur.len[0] : cur.len[2];
+            const int blen = isx ? cur.len[1] : cur.len[3];
+            const int abase = isx ? cur.base[0] : cur.base[2];
+            const int bbase = isx ? cur.base[1] : cur.base[3];
+            const int tot = alen + blen;
+            if (diag >= tot)
+                continue;
+            const LdsPlain<T> P{S, abase};
+            const int boff = bbase - abase;
+            const int i = lds_corank(P, alen, boff, blen, diag);
+            T o[VT];
+            serial_merge<VT>(P, alen, boff, blen, i, diag - i, o);
+            const int obase = isx ? diag : XP + diag;
+            const int cnt = tot - diag < VT ? tot - diag : VT;
+#pragma unroll
+            for (int k = 0; k < VT; ++k)
+                if (k < cnt)
+                    M[obase + k] = o[k];
+        }
+        lds_barrier();
+
+        // level 2: X (+) Y
+        const LdsPlain<T> MX{M, 0};
+        const int diag = t * VT < cur.cnt ? t * VT : cur.cnt;
+        const int i = lds_corank(MX, nxw, XP, nyw, diag);
+        T out[VT];
+        serial_merge<VT>(MX, nxw, XP, nyw, i, diag - i, out);
+        // S was last read by level 1, before the barrier above
+#pragma unroll
+        for (int k = 0; k < VT; ++k)
+            S[cur.shift + t * VT + k] = out[k];
+        lds_barrier();
+
+        const int64_t abs0 = cur.gb + cur.o0 - cur.shift;
+        const int end = cur.shift + cur.cnt;
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int c = t + NT * q;
+            if (4 * c >= end)
+                continue;
+            const int64_t e = abs0 + 4 * c;
+            if (4 * c >= cur.shift && 4 * c + 4 <= end) {
+                if constexpr (sizeof(T) == 4) {
+                    *(int4 *)(kout + e) = *(const int4 *)(S + 4 * c);
+                } else {
+                    const T x0 = S[4 * c], x1 = S[4 * c + 1], x2 = S[4 * c + 2], x3 = S[4 * c + 3];
+                    *(int4 *)(kout + e) =
+                        make_int4(pair_key(x0), pair_key(x1), pair_key(x2), pair_key(x3));
+                    *(int4 *)(vout + e) =
+                        make_int4(pair_val(x0), pair_val(x1), pair_val(x2), pair_val(x3));
+                }
+            } else {
+#pragma unroll
+                for (int q2 = 0; q2 < 4; ++q2)
+                    if (4 * c + q2 >= cur.shift && 4 * c + q2 < end)
+                        store_elem<T>(kout, vout, e + q2, S[4 * c + q2]);
+            }
+        }
+        if (!more)
+            break;
+        g = gn;
+        cur = nxt;
+    }
+}
+
+}  // namespace
+
+bool merge4_supported(int tm, bool pairs)
+{
+    return pairs ? (tm == 2048 || tm == 4096) : (tm == 4096 || tm == 8192);
+}
+
+size_t merge4_record_bytes() { return sizeof(Quad); }
+
+template <typename T>
+static hipError_t launch_quad_corank(const int32_t *kin, const int32_t *vin, int64_t n,
+                                     int64_t run, int64_t tm, void *rec, const CorankOpts &o,
+                                     hipStream_t s)
+{
+    const int64_t ntiles = (n + tm - 1) / tm;
+    CorankCtl c;
+    c.mode = o.mode == 0 ? 0 : 2;  // the four-way search uses the linear prediction
+    c.radius_log2 = o.radius_log2;
+    c.cdf = o.cdf;
+    c.stats = o.stats;
+    c.pair_cdf = nullptr;
+    c.pair_first = 0;
+    hipLaunchKernelGGL(quad_corank_kernel<T>, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0,
+                       s, kin, vin, n, run, tm, ntiles, (Quad *)rec, c);
+    return hipGetLastError();
+}
+
+template <int NT, int VT, typename T>
+static hipError_t launch_m4(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
+                            int64_t n, int64_t run, const void *rec, int occupancy, hipStream_t s)
+{
+    const int64_t ntiles = (n + NT * VT - 1) / (NT * VT);
+    int occ = occupancy;
+    if (occ <= 0 &&
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)merge4_pipe_kernel<NT, VT, T>,
+                                                      NT, 0) != hipSuccess ||
+         occ <= 0))
+        occ = 1;
+    int64_t grid = (int64_t)device_cus() * occ;
+    if (grid > ntiles)
+        grid = ntiles;
+    hipLaunchKernelGGL((merge4_pipe_kernel<NT, VT, T>), dim3((unsigned)grid), dim3(NT), 0, s, kin,
+                       vin, kout, vout, n, run, (const Quad *)rec, ntiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge4_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
+                              int32_t *kout, int32_t *vout, int64_t n, int64_t run, void *rec,
+                              const CorankOpts &o, int occupancy, hipStream_t s)
+{
+    hipError_t e = pairs ? launch_quad_corank<int64_t>(kin, vin, n, run, tm, rec, o, s)
+                         : launch_quad_corank<int32_t>(kin, nullptr, n, run, tm, rec, o, s);
+    if (e != hipSuccess)
+        return e;
+    switch (tm) {
+    case 2048:
+        return pairs ? launch_m4<256, 8, int64_t>(kin, vin, kout, vout, n, run, rec, occupancy, s)
+                     : hipErrorInvalidValue;
+    case 4096:
+        return pairs ? launch_m4<256, 16, int64_t>(kin, vin, kout, vout, n, run, rec, occupancy, s)
+                     : launch_m4<256, 16, int32_t>(kin, vin, kout, vout, n, run, rec, occupancy, s);
+    case 8192:
+        return pairs ? hipErrorInvalidValue
+                     : launch_m4<512, 16, int32_t>(kin, vin, kout, vout, n, run, rec, occupancy, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace hvms

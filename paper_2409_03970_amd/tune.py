@@ -65,13 +65,15 @@ def candidates(op):
     if op == "sort":
         shapes.append((32, 1024))
     out = []
-    for (R, NT), K, TM, V in itertools.product(shapes, (6, 5, 4), (4096, 8192), (2, 3)):
+    for (R, NT), K, TM, V, W in itertools.product(shapes, (6, 5, 4), (4096, 8192), (2, 3), (2, 4)):
         if TM > 2 * R * NT:
             continue
         if op != "sort" and R * NT * 8 > 163840:
             continue
+        if W == 4 and (op == "segmented" or V == 3 or (op == "sort_pairs" and TM != 4096)):
+            continue
         out.append(dict(keys_per_lane=R, block_threads=NT, wave_levels=K + 1, merge_tile=TM,
-                        merge_variant=V))
+                        merge_variant=V, merge_ways=W))
     return out
 
 

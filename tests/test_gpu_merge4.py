@@ -1,0 +1,70 @@
+"""GPU parity of the four-way merge passes (two merge levels per pass)
+against the CPU oracle, bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2409_03970_amd as hv
+from paper_2409_03970_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _check(x, opts):
+    y = hv.sort(x, opts=opts)
+    assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy())), opts
+
+
+@pytest.mark.parametrize("tiles", [2, 3, 4, 5, 7, 8, 9, 16, 17, 33, 64])
+@pytest.mark.parametrize("tm", [4096, 8192])
+def test_four_way_level_counts_and_partial_groups(tiles, tm):
+    # R16 x 256 threads: 4096-key block tiles; odd and even level counts,
+    # groups with 1..3 runs at the end, ragged last run
+    n = tiles * 4096 - (1000 if tiles > 2 else 0)
+    x = inputs.keys(n, "uniform", seed=tiles, device=DEV)
+    _check(x, {"keys_per_lane": 16, "block_threads": 256, "merge_tile": tm, "merge_ways": 4})
+
+
+@pytest.mark.parametrize("dist", list(inputs.DISTRIBUTIONS) + ["mixture"])
+@pytest.mark.parametrize("mode", [hv.CORANK_BINARY, hv.CORANK_LINEAR])
+def test_four_way_distributions(dist, mode):
+    x = inputs.keys(3_000_007, dist, seed=3, device=DEV)
+    _check(x, {"merge_ways": 4, "corank_mode": mode, "radius_log2": 9})
+
+
+@pytest.mark.parametrize("pattern", ["equal", "two_values", "extremes", "negatives"])
+def test_four_way_adversarial(pattern):
+    x = inputs.adversarial_keys(1_000_003, pattern, seed=4, device=DEV)
+    _check(x, {"merge_ways": 4, "merge_tile": 4096})
+
+
+@pytest.mark.parametrize("shape", [(8, 1024), (16, 512), (16, 1024), (32, 256), (32, 512)])
+def test_four_way_tile_shapes(shape):
+    R, NT = shape
+    x = inputs.keys(40 * R * NT + 12345, "zipf", seed=5, device=DEV)
+    _check(x, {"keys_per_lane": R, "block_threads": NT, "merge_ways": 4})
+
+
+@pytest.mark.parametrize("tm", [2048, 4096])
+def test_four_way_pairs(tm):
+    n = 2_000_003
+    k = inputs.keys(n, "distinct16", seed=6, device=DEV)
+    v = torch.randint(-5, 5, (n,), device=DEV, dtype=torch.int32)
+    ko, vo = hv.sort_pairs(k, v, opts={"merge_ways": 4, "merge_tile": tm})
+    ek, ev = oracle.sort_pairs(k.cpu().numpy(), v.cpu().numpy())
+    assert np.array_equal(ko.cpu().numpy(), ek) and np.array_equal(vo.cpu().numpy(), ev)
+
+
+def test_four_way_full_size():
+    n = 1 << 28
+    x = inputs.keys(n, "uniform", seed=0, device=DEV)
+    y = hv.sort(x, opts={"merge_ways": 4})
+    torch.cuda.synchronize()
+    ys, xs = y.cpu().numpy(), x.cpu().numpy()
+    assert np.all(ys[1:] >= ys[:-1])
+    assert oracle.multiset_hash(ys) == oracle.multiset_hash(xs)
+    for p in [0, n // 3, n - 1]:
+        lt, le = oracle.count(xs, ys[p])
+        assert lt <= p < le
