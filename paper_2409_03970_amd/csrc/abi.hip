@@ -89,7 +89,7 @@ int resolve(const hvms_options *o, bool pairs, Cfg &c)
 }
 
 struct SortWs {
-    int64_t scratch_k, scratch_v, coranks, total;
+    int64_t scratch_k, scratch_v, coranks, records, total;
 };
 
 SortWs sort_ws_layout(int64_t n, bool pairs, const Cfg &c)
@@ -104,8 +104,13 @@ SortWs sort_ws_layout(int64_t n, bool pairs, const Cfg &c)
         w.scratch_v = off;
         off += align256(n * 4);
     }
-    w.coranks = off;  // one int64 per tile (two-way) or one record per tile (four-way)
-    off += align256(((n + c.TM - 1) / c.TM + 2) * (int64_t)(c.ways == 4 ? merge4_record_bytes() : 8));
+    const int64_t ntiles = (n + c.TM - 1) / c.TM;
+    w.coranks = off;  // one int64 per tile
+    off += align256((ntiles + 2) * 8);
+    if (c.ways == 4) {  // four-way passes: one co-rank record per tile
+        w.records = off;
+        off += align256((ntiles + 2) * (int64_t)merge4_record_bytes());
+    }
     w.total = off;
     return w;
 }
@@ -156,9 +161,13 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
         int32_t *ok = (dk == kout) ? sk : kout;
         int32_t *ov = (dk == kout) ? sv : vout;
         if (p >= P2) {
+            st = hip_status(launch_merge4_corank(c.TM, pairs, dk, dv, n, run, cr,
+                                                 base + w.records, c.co, s));
+            if (st)
+                return st;
             trace(c, 2 + 2 * p, s);
-            st = hip_status(launch_merge4_pass(c.TM, pairs, dk, dv, ok, ov, n, run, cr, c.co,
-                                               c.occupancy, s));
+            st = hip_status(launch_merge4_pass(c.TM, pairs, dk, dv, ok, ov, n, run,
+                                               base + w.records, c.occupancy, s));
             if (st)
                 return st;
             trace(c, 3 + 2 * p, s);

@@ -259,6 +259,32 @@ template <typename T> struct LdsSkew {
 // Co-rank of diagonal d in the merge of S[0..alen) and S[boff..boff+blen):
 // the number of elements taken from the first run among the first d outputs
 // of the merge that takes the first run on ties.
+// Writes a row of VT elements at position o of a skewed LDS array (o a
+// multiple of 16 bytes' worth of elements, the array's base 0): 16-byte
+// stores when the whole row is valid (consecutive threads' rows then fall in
+// distinct banks), else the first lim elements one by one.
+template <int VT, typename T>
+__device__ __forceinline__ void put_row(const LdsSkew<T> &W, int o, const T (&v)[VT], int lim)
+{
+    constexpr int E = 16 / (int)sizeof(T);
+    typedef T Vec __attribute__((ext_vector_type(E)));
+    if (lim >= VT) {
+#pragma unroll
+        for (int q = 0; q < VT; q += E) {
+            Vec x;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                x[e] = v[q + e];
+            *(Vec *)&W[o + q] = x;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < VT; ++k)
+            if (k < lim)
+                W[o + k] = v[k];
+    }
+}
+
 template <typename V>
 __device__ __forceinline__ int lds_corank(const V &S, int alen, int boff, int blen, int d)
 {
@@ -295,6 +321,40 @@ __device__ __forceinline__ void serial_merge(const V &S, int alen, int boff, int
         a = takeB ? a : nx;
         b = takeB ? nx : b;
     }
+}
+
+// The same VT outputs as serial_merge without a dependent LDS read per
+// output (the hybrid bitonic merge of Sec. 2.4 applied to one thread's share
+// of a merge path): both runs' next VT elements are read at once (positions
+// past a run's end read as the pad value), the flip stage of a bitonic merge
+// keeps the VT smallest of the 2VT as a bitonic sequence, and log2(VT)
+// half-cleaner stages sort it.  Exact because the element order is total on
+// bit patterns (equal elements are identical, and the pad is the maximum).
+// Reads S up to VT - 1 positions past each run's end: the caller's LDS
+// array must extend that far.
+template <int VT, typename V, typename T>
+__device__ __forceinline__ void reg_merge(const V &S, int alen, int boff, int blen, int i, int j,
+                                          T (&out)[VT])
+{
+    T b[VT];
+#pragma unroll
+    for (int k = 0; k < VT; ++k) {
+        const T x = S[i + k];
+        const T y = S[boff + j + k];
+        out[k] = i + k < alen ? x : Traits<T>::kMax;
+        b[k] = j + k < blen ? y : Traits<T>::kMax;
+    }
+#pragma unroll
+    for (int k = 0; k < VT; ++k) {
+        const T y = b[VT - 1 - k];
+        out[k] = y < out[k] ? y : out[k];
+    }
+#pragma unroll
+    for (int h = VT / 2; h >= 1; h >>= 1)
+#pragma unroll
+        for (int k = 0; k < VT; ++k)
+            if (!(k & h))
+                cmpx(out[k], out[k + h]);
 }
 
 // Steps a2-a4 on one tile: v holds each lane's R values (for runs shorter

@@ -35,12 +35,17 @@ hipError_t launch_merge_pass(int tm, bool pairs, const int32_t *kin, const int32
                              const int64_t *cr, int variant, int occupancy, hipStream_t s);
 int device_cus();
 
-// merge4.hip: four-way passes (co-rank records + pipelined merge)
+// merge4.hip: four-way passes (sample grid of two-way co-ranks, co-rank
+// records, pipelined merge); grid: one int64 per tile, rec: one record per
+// tile (merge4_record_bytes), both with room for two more
 bool merge4_supported(int tm, bool pairs);
 size_t merge4_record_bytes();
+hipError_t launch_merge4_corank(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
+                                int64_t n, int64_t run, int64_t *grid, void *rec,
+                                const CorankOpts &o, hipStream_t s);
 hipError_t launch_merge4_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
-                              int32_t *kout, int32_t *vout, int64_t n, int64_t run, void *rec,
-                              const CorankOpts &o, int occupancy, hipStream_t s);
+                              int32_t *kout, int32_t *vout, int64_t n, int64_t run,
+                              const void *rec, int occupancy, hipStream_t s);
 hipError_t launch_corank_list(const int32_t *a, int64_t m, const int32_t *b, int64_t k,
                               const int64_t *diag, int64_t count, int64_t *out,
                               const CorankOpts &o, hipStream_t s);

@@ -6,12 +6,12 @@
 // Output tile g covers [g*TM, (g+1)*TM) of its group.  Its windows follow from
 // three co-ranks of its first diagonal d: x = number of X = A(+)B elements
 // among the first d outputs of X (+) Y (Y = C(+)D), a = co-rank of x in A(+)B,
-// c = co-rank of d - x in C(+)D.  X and Y are never stored, so every probe
-// of the outer search needs an inner co-rank; because co-ranks are monotone,
-// each inner search is confined to the current outer bracket and the total
-// depth is a decreasing series instead of a product.  The merge kernel loads
-// the four windows (TM elements together), merges A with B and C with D in
-// LDS, then the two results, and writes the tile with coalesced stores.
+// c = co-rank of d - x in C(+)D.  X and Y are never stored.  The two-way
+// co-ranks of every tile-aligned diagonal of X and of Y (one launch of the
+// two-way co-rank kernel) form a sample grid that confines x to one interval
+// of TM diagonals; a nested bisection finishes inside it.  The merge kernel
+// loads the four windows (TM elements together), merges A with B and C with
+// D in LDS, then the two results, and writes the tile with coalesced stores.
 #include "hvms_internal.h"
 #include "merge_common.h"
 
@@ -103,69 +103,112 @@ __device__ __forceinline__ Group<T> group_of(const int32_t *k, const int32_t *v,
     return G;
 }
 
-// Outer co-rank x of diagonal d of X (+) Y with the inner co-ranks carried
-// along.  Invariants: x in [lo, hi]; aL = a(lo), aH = a(hi); cL = c(d - hi),
-// cH = c(d - lo) (a, c: co-ranks in X and Y).
+// Two independent bounded co-rank searches (one in X, one in Y), stepped
+// together so that the loads of both are in flight at once.
 template <typename T>
-__device__ Quad quad_corank(const Group<T> &G, int64_t d, const CorankCtl &ctl,
-                            unsigned &probes, unsigned &fallback)
+__device__ __forceinline__ void rank2(const VRun<T> &X, int64_t kx, int64_t lx, int64_t hx,
+                                      int64_t &rx, const VRun<T> &Y, int64_t ky, int64_t ly,
+                                      int64_t hy, int64_t &ry, unsigned &probes)
+{
+    {
+        const int64_t flo = kx > X.nq ? kx - X.nq : 0, fhi = kx < X.np ? kx : X.np;
+        lx = lx < flo ? flo : (lx > fhi ? fhi : lx);
+        hx = hx > fhi ? fhi : (hx < lx ? lx : hx);
+    }
+    {
+        const int64_t flo = ky > Y.nq ? ky - Y.nq : 0, fhi = ky < Y.np ? ky : Y.np;
+        ly = ly < flo ? flo : (ly > fhi ? fhi : ly);
+        hy = hy > fhi ? fhi : (hy < ly ? ly : hy);
+    }
+    while (lx < hx || ly < hy) {
+        const bool sx = lx < hx, sy = ly < hy;
+        const int64_t mx = lx + ((hx - lx) >> 1), my = ly + ((hy - ly) >> 1);
+        T px, qx, py, qy;
+        if (sx) {
+            px = X.P(mx);
+            qx = X.Q(kx - 1 - mx);
+        }
+        if (sy) {
+            py = Y.P(my);
+            qy = Y.Q(ky - 1 - my);
+        }
+        probes += (sx ? 1u : 0u) + (sy ? 1u : 0u);
+        if (sx) {
+            if (qx < px)
+                hx = mx;
+            else
+                lx = mx + 1;
+        }
+        if (sy) {
+            if (qy < py)
+                hy = my;
+            else
+                ly = my + 1;
+        }
+    }
+    rx = lx;
+    ry = ly;
+}
+
+// Co-ranks (x, a, c) of diagonal d (a multiple of tm) of X (+) Y.
+//
+// x is the first m in [lo0, hi0) with Y[d-1-m] < X[m] (hi0 if none).
+// Stage 1 searches the sample grid: the two-way co-ranks a(k*tm) of X and
+// c(k*tm) of Y, which the two-way co-rank kernel computes for every tile of
+// a pass with the same run length (grid[gx + k], grid[gy + k]).  At a grid
+// point m = k*tm the test needs only element loads, since d - m is a grid
+// point of Y too.  That confines x to one interval of tm diagonals.
+// Stage 2 is a bisection inside it; every probe needs a(mid) and
+// c(d-1-mid), each confined to the interval that the current bracket's ends
+// allow (co-ranks are monotone and grow by at most one per diagonal), so
+// the inner searches shrink with the outer one.  Stage 2 invariants: x in
+// [lo, hi]; aL = a(lo), aH = a(hi); cL = c(d - hi), cH = c(d - lo).
+// (A cooperative variant with 16 lanes per tile and 16-way splits cuts the
+// dependent depth about threefold but issues several times the scattered
+// loads, and measured slower.)
+template <typename T>
+__device__ Quad quad_corank(const Group<T> &G, int64_t d, int64_t tm, const int64_t *grid,
+                            int64_t gx, int64_t gy, unsigned &probes)
 {
     const VRun<T> &X = G.X, &Y = G.Y;
     const int64_t nx = X.len(), ny = Y.len();
-    int64_t lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
-    int64_t aL, aH, cL, cH;
-    bool bracketed = false;
-    if (ctl.mode != 0 && hi - lo > 2) {
-        // linear prediction of x and of both inner co-ranks, then an exact
-        // check of the bracket ends; outside the bracket, full search
-        const int64_t r = (int64_t)1 << ctl.radius_log2;
-        const int64_t px = (int64_t)((double)d * (double)nx / (double)(nx + ny));
-        const int64_t L = px - r > lo ? px - r : lo, H = px + r < hi ? px + r : hi;
-        auto inner = [&](const VRun<T> &V, int64_t k) {
-            const int64_t pi = V.len() ? (int64_t)((double)k * (double)V.np / (double)V.len()) : 0;
-            const int64_t flo = k > V.nq ? k - V.nq : 0, fhi = k < V.np ? k : V.np;
-            const int64_t l2 = pi - r > flo ? pi - r : flo, h2 = pi + r < fhi ? pi + r : fhi;
-            ++probes;
-            const bool okl = l2 == flo || !(V.Q(k - l2) < V.P(l2 - 1));
-            const bool okh = h2 == fhi || V.Q(k - 1 - h2) < V.P(h2);
-            if (okl && okh)
-                return V.rank(k, l2, h2, probes);
-            return V.rank(k, flo, fhi, probes);
-        };
-        const int64_t aLb = inner(X, L), aHb = inner(X, H);
-        const int64_t cLb = inner(Y, d - H), cHb = inner(Y, d - L);
-        // x >= L iff L == lo or X[L-1] <= Y[d-L];  x <= H iff H == hi or Y[d-1-H] < X[H]
+    const int64_t lo0 = d > ny ? d - ny : 0, hi0 = d < nx ? d : nx;
+    const int64_t mask = tm - 1;
+    // a(m) / c(k) at a run end or a grid point; elsewhere (the ragged last
+    // group only) by a full search
+    auto ga = [&](int64_t m) {
+        return m == nx ? X.np : ((m & mask) == 0 ? grid[gx + m / tm] : X.rank(m, 0, X.np, probes));
+    };
+    auto gc = [&](int64_t k) {
+        return k == ny ? Y.np : ((k & mask) == 0 ? grid[gy + k / tm] : Y.rank(k, 0, Y.np, probes));
+    };
+
+    // stage 1: first grid point k*tm in [lo0, hi0) whose test holds
+    int64_t klo = (lo0 + mask) / tm, khi = (hi0 + mask) / tm;
+    while (klo < khi) {
+        const int64_t k = (klo + khi) >> 1, m = k * tm;
+        const int64_t am = grid[gx + k];  // m < hi0 <= nx
+        const int64_t ym = d - m;         // in [1, ny], a multiple of tm
+        const int64_t cm = ym == ny ? Y.np : grid[gy + ym / tm];
         bool f;
-        const bool okL = L == lo || !(Y.at(d - L, cHb, f) < X.last(L, aLb));
-        const bool okH = H == hi || Y.last(d - H, cLb) < X.at(H, aHb, f);
         ++probes;
-        if (okL && okH) {
-            lo = L;
-            hi = H;
-            aL = aLb;
-            aH = aHb;
-            cL = cLb;
-            cH = cHb;
-            bracketed = true;
-        } else {
-            fallback = 1;
-        }
+        if (Y.last(ym, cm) < X.at(m, am, f))
+            khi = k;
+        else
+            klo = k + 1;
     }
-    if (!bracketed) {
-        aL = X.rank(lo, 0, X.np, probes);
-        aH = X.rank(hi, 0, X.np, probes);
-        cL = Y.rank(d - hi, 0, Y.np, probes);
-        cH = Y.rank(d - lo, 0, Y.np, probes);
-    }
+    int64_t lo = (klo - 1) * tm > lo0 ? (klo - 1) * tm : lo0;
+    int64_t hi = klo * tm < hi0 ? klo * tm : hi0;
+    int64_t aL = ga(lo), aH = ga(hi), cL = gc(d - hi), cH = gc(d - lo);
+
+    // stage 2
     while (lo < hi) {
         const int64_t mid = lo + ((hi - lo) >> 1);
-        // a(mid) in [max(aL, mid - hi + aH), min(aH, mid - lo + aL)]; y = d - 1 - mid
-        // likewise between c(d - hi) and c(d - lo)
-        const int64_t am = X.rank(mid, aL > mid - hi + aH ? aL : mid - hi + aH,
-                                  aH < mid - lo + aL ? aH : mid - lo + aL, probes);
         const int64_t y = d - 1 - mid;
-        const int64_t ym = Y.rank(y, cL > y - (d - lo) + cH ? cL : y - (d - lo) + cH,
-                                  cH < y - (d - hi) + cL ? cH : y - (d - hi) + cL, probes);
+        int64_t am, ym;
+        rank2<T>(X, mid, aL > mid - hi + aH ? aL : mid - hi + aH, aH < mid - lo + aL ? aH : mid - lo + aL,
+                 am, Y, y, cL > y - (d - lo) + cH ? cL : y - (d - lo) + cH,
+                 cH < y - (d - hi) + cL ? cH : y - (d - hi) + cL, ym, probes);
         bool fx, fy;
         const T xv = X.at(mid, am, fx);
         const T yv = Y.at(y, ym, fy);
@@ -190,8 +233,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void quad_corank_kernel(const int32_t *__restrict__ kin,
                                                           const int32_t *__restrict__ vin,
                                                           int64_t n, int64_t run, int64_t tm,
-                                                          int64_t ntiles, Quad *__restrict__ out,
-                                                          CorankCtl ctl)
+                                                          int64_t ntiles,
+                                                          const int64_t *__restrict__ grid,
+                                                          Quad *__restrict__ out,
+                                                          unsigned long long *stats)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ntiles)
@@ -200,13 +245,11 @@ __global__ __launch_bounds__(256) void quad_corank_kernel(const int32_t *__restr
     const int64_t gq = o0 / (4 * run);
     const Group<T> G = group_of<T>(kin, vin, n, run, gq);
     const int64_t d = o0 - G.gb;
-    unsigned probes = 0, fallback = 0;
-    out[g] = quad_corank<T>(G, d, ctl, probes, fallback);
-    if (ctl.stats) {
-        atomicAdd(ctl.stats + 0, 1ull);
-        atomicAdd(ctl.stats + 1, (unsigned long long)probes);
-        if (ctl.mode != 0)
-            atomicAdd(ctl.stats + 2, (unsigned long long)fallback);
+    unsigned probes = 0;
+    out[g] = quad_corank<T>(G, d, tm, grid, G.gb / tm, (G.gb + 2 * run) / tm, probes);
+    if (stats) {
+        atomicAdd(stats + 0, 1ull);
+        atomicAdd(stats + 1, (unsigned long long)probes);
     }
 }
 
@@ -216,7 +259,6 @@ struct Tile4 {
     int cnt, nx;          // outputs; of them from X = A (+) B
     int len[4], off[4];   // window lengths, offset of window start in its first chunk
     int nch[4], base[4];  // chunks per window, LDS index of window element 0
-    int shift;            // (absolute first output) % 4
 };
 
 // Window geometry of tile g from the co-ranks of its first and next
@@ -264,12 +306,11 @@ __device__ __forceinline__ Tile4 tile4_geo(const Group<T> &G, int64_t run, int64
         t.base[r] = 4 * chunks + t.off[r];
         chunks += t.nch[r];
     }
-    t.shift = (int)((G.gb + t.o0) & 3);
     return t;
 }
 
 template <int NT, int VT, typename T>
-__global__ __launch_bounds__(NT) void merge4_pipe_kernel(const int32_t *__restrict__ kin,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void merge4_pipe_kernel(const int32_t *__restrict__ kin,
                                                          const int32_t *__restrict__ vin,
                                                          int32_t *__restrict__ kout,
                                                          int32_t *__restrict__ vout, int64_t n,
@@ -278,8 +319,12 @@ __global__ __launch_bounds__(NT) void merge4_pipe_kernel(const int32_t *__restri
 {
     constexpr int TM = NT * VT;
     constexpr int CH = VT / 4 + 1;  // chunk slots per thread: TM/4 + 6 chunks at most
-    __shared__ __attribute__((aligned(16))) T S[TM + 32];
-    __shared__ __attribute__((aligned(16))) T M[TM + VT];
+    // S: the four windows (TM elements, up to 24 of chunk alignment, and
+    // VT - 1 read past a window's end by reg_merge); M: the level-1 output in
+    // the skewed layout, so that rows of VT written by consecutive threads
+    // fall in distinct banks
+    __shared__ __attribute__((aligned(16))) T S[TM + 32 + VT];
+    __shared__ __attribute__((aligned(16))) T M[LdsSkew<T>::size(TM + 2 * VT)];
     const int t = threadIdx.x;
     const int64_t first = blockIdx.x, step = gridDim.x, last = ntiles;
     if (first >= last)
@@ -340,7 +385,8 @@ __global__ __launch_bounds__(NT) void merge4_pipe_kernel(const int32_t *__restri
     int64_t rn = g + step < last ? load_rec(g + step) : 0;
 
     for (;;) {
-        lds_barrier();
+        // no barrier needed here: S was last read by level 1 of the previous
+        // tile, and a barrier has followed it since
         const int nc = total_chunks(cur);
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
@@ -362,71 +408,51 @@ __global__ __launch_bounds__(NT) void merge4_pipe_kernel(const int32_t *__restri
             rn = gn + step < last ? load_rec(gn + step) : 0;
         }
 
-        // level 1: X = A (+) B into M[0, nx), Y = C (+) D into M[XP, XP + ny)
+        // level 1: X = A (+) B into M[0, nx), Y = C (+) D into M[nx, cnt).
+        // Thread t produces outputs [t*VT, t*VT + VT) of that concatenation;
+        // the one thread whose range crosses nx also writes the head of Y,
+        // whose co-rank at diagonal 0 is 0 (no search).
         const int nxw = cur.nx, nyw = cur.cnt - cur.nx;
-        const int XP = (nxw + VT - 1) / VT * VT;
-        const int nslots = XP / VT + (nyw + VT - 1) / VT;
-        for (int s = t; s < nslots; s += NT) {
-            const bool isx = s * VT < XP;
-            const int diag = isx ? s * VT : s * VT - XP;
-            const int alen = isx ? cur.len[0] : cur.len[2];
-            const int blen = isx ? cur.len[1] : cur.len[3];
-            const int abase = isx ? cur.base[0] : cur.base[2];
-            const int bbase = isx ? cur.base[1] : cur.base[3];
-            const int tot = alen + blen;
-            if (diag >= tot)
-                continue;
-            const LdsPlain<T> P{S, abase};
-            const int boff = bbase - abase;
-            const int i = lds_corank(P, alen, boff, blen, diag);
-            T o[VT];
-            serial_merge<VT>(P, alen, boff, blen, i, diag - i, o);
-            const int obase = isx ? diag : XP + diag;
-            const int cnt = tot - diag < VT ? tot - diag : VT;
+        {
+            const int o = t * VT;
+            if (o < cur.cnt) {
+                const bool isx = o < nxw;
+                const int diag = isx ? o : o - nxw;
+                const int alen = isx ? cur.len[0] : cur.len[2];
+                const int blen = isx ? cur.len[1] : cur.len[3];
+                const int abase = isx ? cur.base[0] : cur.base[2];
+                const int boff = (isx ? cur.base[1] : cur.base[3]) - abase;
+                const LdsPlain<T> P{S, abase};
+                const int i = lds_corank(P, alen, boff, blen, diag);
+                T v[VT];
+                reg_merge<VT>(P, alen, boff, blen, i, diag - i, v);
+                const LdsSkew<T> MW{M, 0};
+                put_row<VT>(MW, o, v, (isx ? nxw : cur.cnt) - o);
+                if (isx && o + VT > nxw && nyw > 0) {
+                    const LdsPlain<T> Q{S, cur.base[2]};
+                    reg_merge<VT>(Q, cur.len[2], cur.base[3] - cur.base[2], cur.len[3], 0, 0, v);
+                    const int lim2 = (o + VT < cur.cnt ? o + VT : cur.cnt) - nxw;
 #pragma unroll
-            for (int k = 0; k < VT; ++k)
-                if (k < cnt)
-                    M[obase + k] = o[k];
+                    for (int k = 0; k < VT; ++k)
+                        if (k < lim2)
+                            MW[nxw + k] = v[k];
+                }
+            }
         }
         lds_barrier();
 
         // level 2: X (+) Y
-        const LdsPlain<T> MX{M, 0};
+        const LdsSkew<T> MX{M, 0};
         const int diag = t * VT < cur.cnt ? t * VT : cur.cnt;
-        const int i = lds_corank(MX, nxw, XP, nyw, diag);
+        const int i = lds_corank(MX, nxw, nxw, nyw, diag);
         T out[VT];
-        serial_merge<VT>(MX, nxw, XP, nyw, i, diag - i, out);
-        // S was last read by level 1, before the barrier above
-#pragma unroll
-        for (int k = 0; k < VT; ++k)
-            S[cur.shift + t * VT + k] = out[k];
+        reg_merge<VT>(MX, nxw, nxw, nyw, i, diag - i, out);
         lds_barrier();
-
-        const int64_t abs0 = cur.gb + cur.o0 - cur.shift;
-        const int end = cur.shift + cur.cnt;
-#pragma unroll
-        for (int q = 0; q < CH; ++q) {
-            const int c = t + NT * q;
-            if (4 * c >= end)
-                continue;
-            const int64_t e = abs0 + 4 * c;
-            if (4 * c >= cur.shift && 4 * c + 4 <= end) {
-                if constexpr (sizeof(T) == 4) {
-                    *(int4 *)(kout + e) = *(const int4 *)(S + 4 * c);
-                } else {
-                    const T x0 = S[4 * c], x1 = S[4 * c + 1], x2 = S[4 * c + 2], x3 = S[4 * c + 3];
-                    *(int4 *)(kout + e) =
-                        make_int4(pair_key(x0), pair_key(x1), pair_key(x2), pair_key(x3));
-                    *(int4 *)(vout + e) =
-                        make_int4(pair_val(x0), pair_val(x1), pair_val(x2), pair_val(x3));
-                }
-            } else {
-#pragma unroll
-                for (int q2 = 0; q2 < 4; ++q2)
-                    if (4 * c + q2 >= cur.shift && 4 * c + q2 < end)
-                        store_elem<T>(kout, vout, e + q2, S[4 * c + q2]);
-            }
-        }
+        // stage the rows in M (skewed, 16-byte stores), then copy out
+        // coalesced; a tile starts at a multiple of TM, so 16-byte aligned
+        put_row<VT>(MX, diag, out, cur.cnt - diag);
+        lds_barrier();
+        copy_out<NT, CH, T>(MX, kout, vout, cur.gb + cur.o0, cur.cnt, t);
         if (!more)
             break;
         g = gn;
@@ -445,19 +471,12 @@ size_t merge4_record_bytes() { return sizeof(Quad); }
 
 template <typename T>
 static hipError_t launch_quad_corank(const int32_t *kin, const int32_t *vin, int64_t n,
-                                     int64_t run, int64_t tm, void *rec, const CorankOpts &o,
-                                     hipStream_t s)
+                                     int64_t run, int64_t tm, const int64_t *grid, void *rec,
+                                     const CorankOpts &o, hipStream_t s)
 {
     const int64_t ntiles = (n + tm - 1) / tm;
-    CorankCtl c;
-    c.mode = o.mode == 0 ? 0 : 2;  // the four-way search uses the linear prediction
-    c.radius_log2 = o.radius_log2;
-    c.cdf = o.cdf;
-    c.stats = o.stats;
-    c.pair_cdf = nullptr;
-    c.pair_first = 0;
     hipLaunchKernelGGL(quad_corank_kernel<T>, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0,
-                       s, kin, vin, n, run, tm, ntiles, (Quad *)rec, c);
+                       s, kin, vin, n, run, tm, ntiles, grid, (Quad *)rec, o.stats);
     return hipGetLastError();
 }
 
@@ -480,14 +499,25 @@ static hipError_t launch_m4(const int32_t *kin, const int32_t *vin, int32_t *kou
     return hipGetLastError();
 }
 
-hipError_t launch_merge4_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
-                              int32_t *kout, int32_t *vout, int64_t n, int64_t run, void *rec,
-                              const CorankOpts &o, int occupancy, hipStream_t s)
+hipError_t launch_merge4_corank(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
+                                int64_t n, int64_t run, int64_t *grid, void *rec,
+                                const CorankOpts &o, hipStream_t s)
 {
-    hipError_t e = pairs ? launch_quad_corank<int64_t>(kin, vin, n, run, tm, rec, o, s)
-                         : launch_quad_corank<int32_t>(kin, nullptr, n, run, tm, rec, o, s);
+    // the sample grid: two-way co-ranks of every tile-aligned diagonal of the
+    // pairs (A, B) and (C, D) of each group (2*run is a multiple of tm)
+    if (!merge4_supported(tm, pairs) || run <= 0 || (2 * run) % tm != 0)
+        return hipErrorInvalidValue;
+    hipError_t e = launch_pass_corank(pairs, kin, vin, n, run, tm, grid, o, s);
     if (e != hipSuccess)
         return e;
+    return pairs ? launch_quad_corank<int64_t>(kin, vin, n, run, tm, grid, rec, o, s)
+                 : launch_quad_corank<int32_t>(kin, nullptr, n, run, tm, grid, rec, o, s);
+}
+
+hipError_t launch_merge4_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
+                              int32_t *kout, int32_t *vout, int64_t n, int64_t run,
+                              const void *rec, int occupancy, hipStream_t s)
+{
     switch (tm) {
     case 2048:
         return pairs ? launch_m4<256, 8, int64_t>(kin, vin, kout, vout, n, run, rec, occupancy, s)
