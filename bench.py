@@ -88,6 +88,42 @@ def cpu_baseline(dists, log2n, seed=0, sample_log2=24):
                       f"oracle merge sort; {total_s:.1f} s of CPU time"}
 
 
+def merge_passes(n, tile, ways=2):
+    """Merge launches of a sort: the two-way levels first, then (ways = 4)
+    one launch per two levels."""
+    levels = max(0, int(np.ceil(np.log2(max(1, -(-n // tile))))))
+    return levels - (levels // 2 if ways == 4 else 0)
+
+
+def four_way_bench(x, ref_out, opts):
+    """The opt-in four-way merge passes (two merge levels per trip through
+    HBM) against the two-way default on the same input."""
+    o4 = dict(opts, merge_ways=4, merge_variant=0)
+    n = x.numel()
+    tile = (o4.get("keys_per_lane") or 16) * (o4.get("block_threads") or 512)
+    passes = merge_passes(n, tile, 4)
+    ws = torch.empty(max(hv.lib().hvms_sort_workspace_bytes(n, 0, hv._opts(o4)), 1),
+                     dtype=torch.uint8, device=x.device)
+    out = torch.empty_like(x)
+    ms = _median_ms(lambda: hv.hvms_sort_i32(x, out, ws, opts=o4))
+    equal = bool(torch.equal(out, ref_out))
+    ev = make_events(2 + 2 * passes)
+    hv.hvms_sort_i32(x, out, ws, opts=dict(o4, events=ev))
+    torch.cuda.synchronize()
+    merge = [ev[2 + 2 * p].elapsed_time(ev[3 + 2 * p]) for p in range(passes)]
+    # launches between two merge launches: the co-rank grid and the
+    # four-way co-rank records of the next pass
+    corank = [ev[1 + 2 * p].elapsed_time(ev[2 + 2 * p]) for p in range(passes)]
+    levels = max(0, int(np.ceil(np.log2(max(1, -(-n // tile))))))
+    p2 = levels - 2 * (levels // 2)  # two-way launches come first
+    four = merge[p2:]
+    return {"ms": round(ms, 3), "gkeys_per_s": round(n / ms / 1e6, 3), "merge_launches": passes,
+            "two_way_launches": p2, "options": o4, "merge_ms": [round(t, 3) for t in merge],
+            "corank_ms": [round(t, 3) for t in corank],
+            "four_way_pass_gbs_mean": round(8.0 * n / (np.mean(four) / 1e3) / 1e9, 1) if four else None,
+            "block_sort_ms": round(ev[0].elapsed_time(ev[1]), 3), "equal_to_two_way": equal}
+
+
 def _median_ms(fn, reps=3):
     fn()
     torch.cuda.synchronize()
@@ -146,7 +182,7 @@ def pairs_bench(n):
     opts = tune.tuned_options("sort_pairs", n) or {}
     ws = hv._workspace(hv.lib().hvms_sort_workspace_bytes(n, 1, hv._opts(opts)), dev)
     tile = (opts.get("keys_per_lane") or 16) * (opts.get("block_threads") or 512)
-    passes = int(np.ceil(np.log2(-(-n // tile))))
+    passes = merge_passes(n, tile, opts.get("merge_ways") or 2)
     ev = make_events(2 + 2 * passes)
     ms = _median_ms(lambda: hv.hvms_sort_pairs_i32(k, v, ko, vo, ws, opts=opts))
     hv.hvms_sort_pairs_i32(k, v, ko, vo, ws, opts=dict(opts, events=ev))
@@ -413,7 +449,7 @@ def main():
     R = opts.get("keys_per_lane") or 16
     NT = opts.get("block_threads") or 512
     tile = R * NT
-    passes = max(0, int(np.ceil(np.log2(max(1, -(-n // tile))))))
+    passes = merge_passes(n, tile, opts.get("merge_ways") or 2)
 
     log(f"generating {len(dists)} x 2^{log2n} keys")
     xs = [inputs.keys(n, d, seed=0, device=dev) for d in dists]
@@ -493,6 +529,7 @@ def main():
             "block_tile": tile, "merge_tile": opts.get("merge_tile") or min(8192, 2 * tile),
             "wave_levels": (opts.get("wave_levels") or 7) - 1,
             "merge_variant": opts.get("merge_variant") or 2, "merge_passes": passes,
+            "merge_ways": opts.get("merge_ways") or 2,
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -516,6 +553,12 @@ def main():
             rec["corank_modes_2p28"] = corank_modes(xs, dists, out, ws, opts)
         except Exception as e:  # an extra must never cost the headline line
             rec["corank_modes_2p28"] = {"error": repr(e)}
+        log("four_way_2p28")
+        try:
+            hv.hvms_sort_i32(xs[0], out, ws, opts=opts)
+            rec["four_way_2p28_" + dists[0]] = four_way_bench(xs[0], out, opts)
+        except Exception as e:
+            rec["four_way_2p28_" + dists[0]] = {"error": repr(e)}
         del xs, out, ws, ev_sets
         torch.cuda.empty_cache()
         extras = (("in_register_sort_table2", table2_bench),

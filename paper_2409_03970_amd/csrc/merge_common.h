@@ -360,32 +360,6 @@ template <typename T> __device__ __forceinline__ void put_chunk(T *S, int c, con
 
 // n_abs: length of the arrays (for the ragged last chunk).  Arrays must be
 // 16-byte aligned.
-// Writes VT consecutive outputs from registers to global index e (a
-// multiple of 4): 16-byte stores when all are valid, else the first lim.
-template <int VT, typename T>
-__device__ __forceinline__ void store_row(int32_t *__restrict__ k, int32_t *__restrict__ v,
-                                          int64_t e, const T (&x)[VT], int lim)
-{
-    if (lim >= VT) {
-#pragma unroll
-        for (int q = 0; q < VT; q += 4) {
-            if constexpr (sizeof(T) == 4) {
-                *(int4 *)(k + e + q) = make_int4(x[q], x[q + 1], x[q + 2], x[q + 3]);
-            } else {
-                *(int4 *)(k + e + q) = make_int4(pair_key(x[q]), pair_key(x[q + 1]),
-                                                 pair_key(x[q + 2]), pair_key(x[q + 3]));
-                *(int4 *)(v + e + q) = make_int4(pair_val(x[q]), pair_val(x[q + 1]),
-                                                 pair_val(x[q + 2]), pair_val(x[q + 3]));
-            }
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < VT; ++q)
-            if (q < lim)
-                store_elem<T>(k, v, e + q, x[q]);
-    }
-}
-
 // Coalesced copy of the first cnt elements of a skewed LDS array to global
 // index abs0 (a multiple of 4): thread t moves 16-byte chunks t, t + NT, ...
 template <int NT, int CH, typename T>
@@ -433,10 +407,7 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
 {
     constexpr int TM = NT * VT;
     constexpr int CH = VT / 4 + 1;  // chunk slots per thread: TM/4 + 3 chunks at most
-    // input windows (TM elements, up to 6 of chunk alignment, VT - 1 read
-    // past a window's end by reg_merge) or the skewed output rows
-    constexpr int SN = LdsSkew<T>::size(TM) > TM + 16 + VT ? LdsSkew<T>::size(TM) : TM + 16 + VT;
-    __shared__ __attribute__((aligned(16))) T S[SN];
+    __shared__ __attribute__((aligned(16))) T S[TM + 16];
     const int t = threadIdx.x;
     const int64_t ntiles = map.count();
 
@@ -529,21 +500,8 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
         const int diag = t * VT < cur.cnt ? t * VT : cur.cnt;
         const int i = lds_corank(A, cur.acnt, boff, cur.bcnt, diag);
         T out[VT];
-        reg_merge<VT>(A, cur.acnt, boff, cur.bcnt, i, diag - i, out);
+        serial_merge<VT>(A, cur.acnt, boff, cur.bcnt, i, diag - i, out);
         lds_barrier();
-        if (cur.shift == 0) {
-            // the tile starts 16-byte aligned: stage the rows in the skewed
-            // layout (16-byte stores, no bank conflicts), then copy out
-            const LdsSkew<T> W{S, 0};
-            put_row<VT>(W, diag, out, cur.cnt - diag);
-            lds_barrier();
-            copy_out<NT, CH, T>(W, cur.r.ok, cur.r.ov, cur.r.base + cur.o0, cur.cnt, t);
-            if (!more)
-                break;
-            g = gn;
-            cur = nxt;
-            continue;
-        }
 #pragma unroll
         for (int k = 0; k < VT; ++k)
             S[cur.shift + t * VT + k] = out[k];
