@@ -37,6 +37,11 @@ def lib():
         L = ctypes.CDLL(_SO)
         L.oracle_sort_i32.argtypes = [_i32p, ctypes.c_int64]
         L.oracle_sort_pairs_i32.argtypes = [_i32p, _i32p, ctypes.c_int64]
+        _u32p = ctypes.POINTER(ctypes.c_uint32)
+        for name in ("oracle_sort_u32", "oracle_sort_f32"):
+            getattr(L, name).argtypes = [_u32p, ctypes.c_int64]
+        for name in ("oracle_sort_pairs_u32", "oracle_sort_pairs_f32"):
+            getattr(L, name).argtypes = [_u32p, _i32p, ctypes.c_int64]
         L.oracle_segmented_sort_i32.argtypes = [_i32p, _i64p, ctypes.c_int64]
         L.oracle_segmented_sort_pairs_i32.argtypes = [_i32p, _i32p, _i64p, ctypes.c_int64]
         L.oracle_merge_i32.argtypes = [_i32p, ctypes.c_int64, _i32p, ctypes.c_int64, _i32p]
@@ -88,6 +93,47 @@ def sort_pairs(keys, vals):
     if lib().oracle_sort_pairs_i32(pk, pv, k.size) != 0:
         raise MemoryError("oracle pair sort failed")
     return k, v
+
+
+def _bits(keys, dtype):
+    """A uint32 copy of the keys' bit patterns (keys given as `dtype`)."""
+    return np.ascontiguousarray(np.array(keys, dtype=dtype, copy=True).view(np.uint32))
+
+
+def sort_u32(keys):
+    """Sorted copy of uint32 keys (unsigned order)."""
+    a = _bits(keys, np.uint32)
+    if lib().oracle_sort_u32(a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), a.size) != 0:
+        raise MemoryError("oracle sort failed")
+    return a
+
+
+def sort_f32(keys):
+    """Sorted copy of float32 keys in IEEE 754 totalOrder (bit-exact: -0
+    before +0, NaNs placed by sign and payload)."""
+    a = _bits(keys, np.float32)
+    if lib().oracle_sort_f32(a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), a.size) != 0:
+        raise MemoryError("oracle sort failed")
+    return a.view(np.float32)
+
+
+def _sort_pairs_gen(fn, a, vals):
+    v, pv = _i32(np.array(vals, dtype=np.int32, copy=True))
+    assert a.size == v.size
+    if fn(a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), pv, a.size) != 0:
+        raise MemoryError("oracle pair sort failed")
+    return a, v
+
+
+def sort_pairs_u32(keys, vals):
+    """(keys, vals) sorted by (unsigned key, signed value)."""
+    return _sort_pairs_gen(lib().oracle_sort_pairs_u32, _bits(keys, np.uint32), vals)
+
+
+def sort_pairs_f32(keys, vals):
+    """(keys, vals) sorted by (key in IEEE 754 totalOrder, signed value)."""
+    k, v = _sort_pairs_gen(lib().oracle_sort_pairs_f32, _bits(keys, np.float32), vals)
+    return k.view(np.float32), v
 
 
 def segmented_sort(keys, offsets):

@@ -127,6 +127,102 @@ int oracle_sort_pairs_i32(int32_t *k, int32_t *v, int64_t n)
     return 0;
 }
 
+/* ------------------------------------------- unsigned and float32 keys */
+
+/*
+ * Other 32-bit key types, each with the order written out directly:
+ *   - uint32: unsigned order;
+ *   - float32: the totalOrder predicate of IEEE 754-2008 (5.10) on the bit
+ *     patterns: negative values (sign bit set) before positive ones; among
+ *     positives the larger magnitude field (exponent and fraction read as
+ *     one unsigned integer) is larger, among negatives it is smaller.  So
+ *     -NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN, NaNs ordered by
+ *     payload.
+ * Pairs carry a signed int32 value and order lexicographically (key, value).
+ * The merge sort is the same top-down stable merge sort as above, with the
+ * key comparison passed in.
+ */
+typedef int (*less32_fn)(uint32_t, uint32_t);
+
+static int less_u32(uint32_t a, uint32_t b) { return a < b; }
+
+static int less_f32_total(uint32_t a, uint32_t b)
+{
+    uint32_t sa = a >> 31, sb = b >> 31;
+    if (sa != sb)
+        return sa > sb;
+    uint32_t ma = a & 0x7fffffffu, mb = b & 0x7fffffffu;
+    return sa ? ma > mb : ma < mb;
+}
+
+static int gpair_less(less32_fn less, uint32_t ka, int32_t va, uint32_t kb, int32_t vb)
+{
+    if (less(ka, kb))
+        return 1;
+    if (less(kb, ka))
+        return 0;
+    return va < vb;
+}
+
+/* v may be NULL (keys only) */
+static void msort_gen(less32_fn less, uint32_t *k, int32_t *v, uint32_t *auxk, int32_t *auxv,
+                      int64_t lo, int64_t hi)
+{
+    if (hi - lo < 2)
+        return;
+    int64_t mid = lo + (hi - lo) / 2;
+    msort_gen(less, k, v, auxk, auxv, lo, mid);
+    msort_gen(less, k, v, auxk, auxv, mid, hi);
+    int64_t i = lo, j = mid, o = lo;
+    while (i < mid || j < hi) {
+        int take_j;
+        if (i == mid)
+            take_j = 1;
+        else if (j == hi)
+            take_j = 0;
+        else
+            take_j = v ? gpair_less(less, k[j], v[j], k[i], v[i]) : less(k[j], k[i]);
+        int64_t src = take_j ? j++ : i++;
+        auxk[o] = k[src];
+        if (v)
+            auxv[o] = v[src];
+        ++o;
+    }
+    memcpy(k + lo, auxk + lo, (size_t)(hi - lo) * sizeof(uint32_t));
+    if (v)
+        memcpy(v + lo, auxv + lo, (size_t)(hi - lo) * sizeof(int32_t));
+}
+
+static int sort_gen(less32_fn less, uint32_t *k, int32_t *v, int64_t n)
+{
+    if (n < 0)
+        return -1;
+    if (n < 2)
+        return 0;
+    uint32_t *auxk = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    int32_t *auxv = v ? (int32_t *)malloc((size_t)n * sizeof(int32_t)) : NULL;
+    if (!auxk || (v && !auxv)) {
+        free(auxk);
+        free(auxv);
+        return -1;
+    }
+    msort_gen(less, k, v, auxk, auxv, 0, n);
+    free(auxk);
+    free(auxv);
+    return 0;
+}
+
+int oracle_sort_u32(uint32_t *k, int64_t n) { return sort_gen(less_u32, k, NULL, n); }
+int oracle_sort_f32(uint32_t *bits, int64_t n) { return sort_gen(less_f32_total, bits, NULL, n); }
+int oracle_sort_pairs_u32(uint32_t *k, int32_t *v, int64_t n)
+{
+    return sort_gen(less_u32, k, v, n);
+}
+int oracle_sort_pairs_f32(uint32_t *bits, int32_t *v, int64_t n)
+{
+    return sort_gen(less_f32_total, bits, v, n);
+}
+
 /* ------------------------------------------------------------- segmented */
 
 /* Segment s is k[offs[s] .. offs[s+1]); offsets must be nondecreasing. */

@@ -1,0 +1,80 @@
+"""Pins of the oracle's uint32 and float32 sorts: numpy's sort where its
+order is the same (unsigned integers; finite nonzero floats), the IEEE 754
+totalOrder sequence of special values (tests/golden/f32_total_order.txt),
+and lexicographic pair order against numpy's lexsort."""
+import numpy as np
+import pytest
+
+import oracle
+
+
+def _golden(golden_dir):
+    rows = []
+    with open(f"{golden_dir}/f32_total_order.txt") as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append(int(line.split()[0], 16))
+    return np.array(rows, dtype=np.uint32)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 1000, 100003])
+def test_u32_matches_numpy(n):
+    rng = np.random.default_rng(n)
+    x = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
+    x[: n // 10] = rng.choice(np.array([0, 1, 2**31 - 1, 2**31, 2**32 - 1], dtype=np.uint32),
+                             size=n // 10)
+    assert np.array_equal(oracle.sort_u32(x), np.sort(x))
+
+
+@pytest.mark.parametrize("n", [1, 5, 4097, 100003])
+def test_f32_finite_nonzero_matches_numpy(n):
+    rng = np.random.default_rng(7 + n)
+    x = (rng.standard_normal(n) * 10.0 ** rng.integers(-30, 30, size=n)).astype(np.float32)
+    x[x == 0] = 1.0
+    got = oracle.sort_f32(x)
+    assert np.array_equal(got.view(np.uint32), np.sort(x).view(np.uint32))
+
+
+def test_f32_special_values_follow_total_order(golden_dir):
+    want = _golden(golden_dir)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        x = rng.permutation(np.repeat(want, 3))
+        got = oracle.sort_f32(x.view(np.float32)).view(np.uint32)
+        assert np.array_equal(got, np.repeat(want, 3))
+
+
+def test_f32_signed_zero_and_nan_placement():
+    x = np.array([0.0, -0.0, np.nan, -np.nan, -np.inf, np.inf, 1.0, -1.0], dtype=np.float32)
+    got = oracle.sort_f32(x).view(np.uint32)
+    signs = got >> 31
+    # negatives (sign set) first, and within them -NaN, -inf, -1, -0
+    assert list(signs) == [1, 1, 1, 1, 0, 0, 0, 0]
+    v = got.view(np.float32)
+    assert np.isnan(v[0]) and v[1] == -np.inf and v[2] == -1.0 and v[3] == 0 and signs[3] == 1
+    assert v[4] == 0 and signs[4] == 0 and v[5] == 1.0 and v[6] == np.inf and np.isnan(v[7])
+
+
+@pytest.mark.parametrize("kind", ["u32", "f32"])
+def test_pairs_lexicographic(kind):
+    rng = np.random.default_rng(11)
+    n = 20011
+    if kind == "u32":
+        k = rng.choice(np.array([0, 5, 2**31, 2**32 - 1], dtype=np.uint32), size=n)
+        ko, vo = oracle.sort_pairs_u32(k, v := rng.integers(-50, 50, size=n).astype(np.int32))
+        order = np.lexsort((v, k))
+        assert np.array_equal(ko, k[order]) and np.array_equal(vo, v[order])
+    else:
+        k = rng.choice(np.array([-3.5, -1.0, 2.0, 1e30, -1e-30], dtype=np.float32), size=n)
+        ko, vo = oracle.sort_pairs_f32(k, v := rng.integers(-50, 50, size=n).astype(np.int32))
+        order = np.lexsort((v, k))
+        assert np.array_equal(ko.view(np.uint32), k[order].view(np.uint32))
+        assert np.array_equal(vo, v[order])
+
+
+def test_pairs_f32_signed_zeros_order_by_sign_first():
+    k = np.array([0.0, -0.0, 0.0, -0.0], dtype=np.float32)
+    v = np.array([1, 2, -1, -2], dtype=np.int32)
+    ko, vo = oracle.sort_pairs_f32(k, v)
+    assert list(ko.view(np.uint32) >> 31) == [1, 1, 0, 0]
+    assert list(vo) == [-2, 2, -1, 1]
