@@ -137,6 +137,34 @@ int hvms_sort_pairs_i32(const int32_t *d_keys_in, const int32_t *d_vals_in,
                         const hvms_options *opt);
 
 /*
+ * Other 32-bit key types (the paper sorts 32-bit integers "as an example",
+ * Sec. 2.1): the same sort with an order-preserving bit map of the keys onto
+ * int32 order applied as the keys are first loaded and undone as they are
+ * finally stored, so no pass over memory is added.
+ *   hvms_sort_u32:  unsigned order.
+ *   hvms_sort_f32:  IEEE 754 totalOrder of the bit patterns: -NaN < -inf <
+ *                   ... < -0 < +0 < ... < +inf < +NaN, NaNs of one sign by
+ *                   payload (larger payload further from zero); every bit
+ *                   pattern is preserved.
+ *   *_pairs_*:      (key, value) pairs, lexicographic with signed int32
+ *                   values, as hvms_sort_pairs_i32.
+ * Arguments, workspace (hvms_sort_workspace_bytes with the same pairs flag),
+ * aliasing and errors as hvms_sort_i32 / hvms_sort_pairs_i32.
+ */
+int hvms_sort_u32(const uint32_t *d_in, uint32_t *d_out, int64_t n, void *d_ws,
+                  size_t ws_bytes, void *stream, const hvms_options *opt);
+int hvms_sort_f32(const float *d_in, float *d_out, int64_t n, void *d_ws,
+                  size_t ws_bytes, void *stream, const hvms_options *opt);
+int hvms_sort_pairs_u32(const uint32_t *d_keys_in, const int32_t *d_vals_in,
+                        uint32_t *d_keys_out, int32_t *d_vals_out, int64_t n,
+                        void *d_ws, size_t ws_bytes, void *stream,
+                        const hvms_options *opt);
+int hvms_sort_pairs_f32(const float *d_keys_in, const int32_t *d_vals_in,
+                        float *d_keys_out, int32_t *d_vals_out, int64_t n,
+                        void *d_ws, size_t ws_bytes, void *stream,
+                        const hvms_options *opt);
+
+/*
  * Sort every run of 2^run_log2 consecutive keys independently (the last run
  * may be shorter): the block stage alone, i.e. "every X elements in order"
  * of Table 2 with X = 2^run_log2.  run_log2 must lie in

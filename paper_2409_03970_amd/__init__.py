@@ -21,7 +21,8 @@ __all__ = [
     "sort", "sort_pairs", "sort_runs", "merge_pass", "corank", "segmented_sort",
     "segmented_sort_pairs", "cdf_forward", "cdf_backward", "cdf_adam_step", "cdf_train",
     "hvms_cdf_sample_i32", "cdf_sample", "fit_cdf_model", "segmented_sort_pairs_grouped",
-    "segment_groups",
+    "segment_groups", "hvms_sort_u32", "hvms_sort_f32", "hvms_sort_pairs_u32",
+    "hvms_sort_pairs_f32", "sort_keys", "sort_pairs_keys",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -75,6 +76,10 @@ _SIGS = {
     "hvms_sort_i32": ([_vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
     "hvms_sort_pairs_i32": ([_vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
     "hvms_sort_runs_i32": ([_vp, _vp, _i64, _i32, _vp, _opt], _i32),
+    "hvms_sort_u32": ([_vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
+    "hvms_sort_f32": ([_vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
+    "hvms_sort_pairs_u32": ([_vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
+    "hvms_sort_pairs_f32": ([_vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
     "hvms_merge_workspace_bytes": ([_i64, _i64, _opt], _i64),
     "hvms_merge_pass_i32": ([_vp, _vp, _i64, _i64, _vp, _sz, _vp, _opt], _i32),
     "hvms_corank_i32": ([_vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _opt], _i32),
@@ -186,6 +191,46 @@ def hvms_sort_pairs_i32(k_in, v_in, k_out, v_out, ws=None, stream=None, opts=Non
         _ptr(v_out, torch.int32), k_in.numel(), p, b, _stream(stream), _opts(opts)))
 
 
+# uint32 keys may come as torch.uint32 or as int32 bit patterns
+_KEY_DTYPES = {"u32": (torch.uint32, torch.int32), "f32": (torch.float32,)}
+
+
+def _kptr(t, kind, name):
+    if t.dtype not in _KEY_DTYPES[kind]:
+        raise ValueError(f"{name} must be one of {_KEY_DTYPES[kind]}, got {t.dtype}")
+    return _ptr(t, None, name)
+
+
+def hvms_sort_u32(d_in, d_out, ws=None, stream=None, opts=None):
+    p, b = _wsargs(ws)
+    _check("hvms_sort_u32", lib().hvms_sort_u32(
+        _kptr(d_in, "u32", "in"), _kptr(d_out, "u32", "out"), d_in.numel(), p, b,
+        _stream(stream), _opts(opts)))
+
+
+def hvms_sort_f32(d_in, d_out, ws=None, stream=None, opts=None):
+    p, b = _wsargs(ws)
+    _check("hvms_sort_f32", lib().hvms_sort_f32(
+        _kptr(d_in, "f32", "in"), _kptr(d_out, "f32", "out"), d_in.numel(), p, b,
+        _stream(stream), _opts(opts)))
+
+
+def _sort_pairs_mapped(fn, kind, k_in, v_in, k_out, v_out, ws, stream, opts):
+    assert k_in.numel() == v_in.numel() == k_out.numel() == v_out.numel()
+    p, b = _wsargs(ws)
+    _check(fn, getattr(lib(), fn)(
+        _kptr(k_in, kind, "keys"), _ptr(v_in, torch.int32), _kptr(k_out, kind, "keys_out"),
+        _ptr(v_out, torch.int32), k_in.numel(), p, b, _stream(stream), _opts(opts)))
+
+
+def hvms_sort_pairs_u32(k_in, v_in, k_out, v_out, ws=None, stream=None, opts=None):
+    _sort_pairs_mapped("hvms_sort_pairs_u32", "u32", k_in, v_in, k_out, v_out, ws, stream, opts)
+
+
+def hvms_sort_pairs_f32(k_in, v_in, k_out, v_out, ws=None, stream=None, opts=None):
+    _sort_pairs_mapped("hvms_sort_pairs_f32", "f32", k_in, v_in, k_out, v_out, ws, stream, opts)
+
+
 def hvms_sort_runs_i32(d_in, d_out, run_log2, stream=None, opts=None):
     _check("hvms_sort_runs_i32", lib().hvms_sort_runs_i32(
         _ptr(d_in, torch.int32), _ptr(d_out, torch.int32), d_in.numel(), int(run_log2),
@@ -283,6 +328,37 @@ def sort_pairs(keys, vals, keys_out=None, vals_out=None, opts=None, stream=None)
     vals_out = torch.empty_like(vals) if vals_out is None else vals_out
     ws = _workspace(lib().hvms_sort_workspace_bytes(keys.numel(), 1, _opts(opts)), keys.device)
     hvms_sort_pairs_i32(keys, vals, keys_out, vals_out, ws, stream, opts)
+    return keys_out, vals_out
+
+
+def sort_keys(keys, out=None, opts=None, stream=None):
+    """Sorted copy of a device tensor of int32, uint32 (torch.uint32) or
+    float32 keys (IEEE 754 totalOrder); out may be keys (in place)."""
+    if keys.dtype == torch.int32:
+        return sort(keys, out, opts, stream)
+    fn = {torch.uint32: hvms_sort_u32, torch.float32: hvms_sort_f32}.get(keys.dtype)
+    if fn is None:
+        raise ValueError(f"unsupported key dtype {keys.dtype}")
+    opts = _auto("sort", keys.numel(), opts)
+    out = torch.empty_like(keys) if out is None else out
+    ws = _workspace(lib().hvms_sort_workspace_bytes(keys.numel(), 0, _opts(opts)), keys.device)
+    fn(keys, out, ws, stream, opts)
+    return out
+
+
+def sort_pairs_keys(keys, vals, keys_out=None, vals_out=None, opts=None, stream=None):
+    """sort_pairs for int32, uint32 (torch.uint32) or float32 keys with int32
+    values, lexicographic (key, value)."""
+    if keys.dtype == torch.int32:
+        return sort_pairs(keys, vals, keys_out, vals_out, opts, stream)
+    fn = {torch.uint32: hvms_sort_pairs_u32, torch.float32: hvms_sort_pairs_f32}.get(keys.dtype)
+    if fn is None:
+        raise ValueError(f"unsupported key dtype {keys.dtype}")
+    opts = _auto("sort_pairs", keys.numel(), opts)
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    vals_out = torch.empty_like(vals) if vals_out is None else vals_out
+    ws = _workspace(lib().hvms_sort_workspace_bytes(keys.numel(), 1, _opts(opts)), keys.device)
+    fn(keys, vals, keys_out, vals_out, ws, stream, opts)
     return keys_out, vals_out
 
 

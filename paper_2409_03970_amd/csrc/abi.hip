@@ -124,8 +124,10 @@ int check_ws(void *ws, size_t bytes, int64_t need)
     return HVMS_OK;
 }
 
+// km: the key map of a uint32 or float32 sort, applied as the keys are
+// loaded by the block stage and undone as the last launch stores them.
 int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
-             int64_t n, void *ws, hipStream_t s, const Cfg &c)
+             int64_t n, void *ws, hipStream_t s, const Cfg &c, KeyMap km = {})
 {
     const int64_t tile = (int64_t)c.R * c.NT;
     const int lanes_log2 = ilog2_exact(c.NT);  // levels from R-runs to the tile
@@ -134,7 +136,7 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
     if (n <= tile)
         return hip_status(
             launch_block_sort(c.R, c.NT, pairs, kin, vin, kout, vout, n, K, lds_levels, false, s,
-                              c.net));
+                              c.net, km, km));
 
     const SortWs w = sort_ws_layout(n, pairs, c);
     char *base = (char *)ws;
@@ -152,7 +154,7 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
     trace(c, 0, s);
     int st = hip_status(
         launch_block_sort(c.R, c.NT, pairs, kin, vin, dk, dv, n, K, lds_levels, false, s,
-                          c.net));
+                          c.net, km, passes == 0 ? km : KeyMap{}));
     if (st)
         return st;
     trace(c, 1, s);
@@ -167,7 +169,8 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
                 return st;
             trace(c, 2 + 2 * p, s);
             st = hip_status(launch_merge4_pass(c.TM, pairs, dk, dv, ok, ov, n, run,
-                                               base + w.records, c.occupancy, s));
+                                               base + w.records, c.occupancy, s,
+                                               p == passes - 1 ? km : KeyMap{}));
             if (st)
                 return st;
             trace(c, 3 + 2 * p, s);
@@ -181,7 +184,7 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
             return st;
         trace(c, 2 + 2 * p, s);
         st = hip_status(launch_merge_pass(c.TM, pairs, dk, dv, ok, ov, n, run, cr, c.variant,
-                                          c.occupancy, s));
+                                          c.occupancy, s, p == passes - 1 ? km : KeyMap{}));
         if (st)
             return st;
         trace(c, 3 + 2 * p, s);
@@ -255,6 +258,89 @@ int hvms_sort_pairs_i32(const int32_t *d_keys_in, const int32_t *d_vals_in, int3
         return st;
     return run_sort(true, d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, d_ws,
                     (hipStream_t)stream, c);
+}
+
+}  // extern "C"
+
+namespace {
+
+KeyMap key_map_of(int kind)  // 1 uint32, 2 float32
+{
+    KeyMap m;
+    if (kind == 1)
+        m.um = (int32_t)0x80000000u;
+    else
+        m.fm = 0x7fffffff;
+    return m;
+}
+
+int sort_keys_mapped(const void *d_in, void *d_out, int64_t n, void *d_ws, size_t ws_bytes,
+                     void *stream, const hvms_options *opt, int kind)
+{
+    if (n < 0 || (n > 0 && (!d_in || !d_out)))
+        return HVMS_ERR_INVALID_ARG;
+    Cfg c;
+    int st = resolve(opt, false, c);
+    if (st)
+        return st;
+    if (n == 0)
+        return HVMS_OK;
+    st = check_ws(d_ws, ws_bytes, sort_ws_layout(n, false, c).total);
+    if (st)
+        return st;
+    return run_sort(false, (const int32_t *)d_in, nullptr, (int32_t *)d_out, nullptr, n, d_ws,
+                    (hipStream_t)stream, c, key_map_of(kind));
+}
+
+int sort_pairs_mapped(const void *d_keys_in, const int32_t *d_vals_in, void *d_keys_out,
+                      int32_t *d_vals_out, int64_t n, void *d_ws, size_t ws_bytes, void *stream,
+                      const hvms_options *opt, int kind)
+{
+    if (n < 0 || (n > 0 && (!d_keys_in || !d_vals_in || !d_keys_out || !d_vals_out)))
+        return HVMS_ERR_INVALID_ARG;
+    Cfg c;
+    int st = resolve(opt, true, c);
+    if (st)
+        return st;
+    if (n == 0)
+        return HVMS_OK;
+    st = check_ws(d_ws, ws_bytes, sort_ws_layout(n, true, c).total);
+    if (st)
+        return st;
+    return run_sort(true, (const int32_t *)d_keys_in, d_vals_in, (int32_t *)d_keys_out,
+                    d_vals_out, n, d_ws, (hipStream_t)stream, c, key_map_of(kind));
+}
+
+}  // namespace
+
+extern "C" {
+
+int hvms_sort_u32(const uint32_t *d_in, uint32_t *d_out, int64_t n, void *d_ws, size_t ws_bytes,
+                  void *stream, const hvms_options *opt)
+{
+    return sort_keys_mapped(d_in, d_out, n, d_ws, ws_bytes, stream, opt, 1);
+}
+
+int hvms_sort_f32(const float *d_in, float *d_out, int64_t n, void *d_ws, size_t ws_bytes,
+                  void *stream, const hvms_options *opt)
+{
+    return sort_keys_mapped(d_in, d_out, n, d_ws, ws_bytes, stream, opt, 2);
+}
+
+int hvms_sort_pairs_u32(const uint32_t *d_keys_in, const int32_t *d_vals_in, uint32_t *d_keys_out,
+                        int32_t *d_vals_out, int64_t n, void *d_ws, size_t ws_bytes,
+                        void *stream, const hvms_options *opt)
+{
+    return sort_pairs_mapped(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, d_ws, ws_bytes,
+                             stream, opt, 1);
+}
+
+int hvms_sort_pairs_f32(const float *d_keys_in, const int32_t *d_vals_in, float *d_keys_out,
+                        int32_t *d_vals_out, int64_t n, void *d_ws, size_t ws_bytes,
+                        void *stream, const hvms_options *opt)
+{
+    return sort_pairs_mapped(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, d_ws, ws_bytes,
+                             stream, opt, 2);
 }
 
 int hvms_sort_runs_i32(const int32_t *d_in, int32_t *d_out, int64_t n, int32_t run_log2,

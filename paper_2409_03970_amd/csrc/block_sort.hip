@@ -24,7 +24,7 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
                                                         int32_t *__restrict__ kout,
                                                         int32_t *__restrict__ vout, int64_t n,
                                                         int wave_levels, int lds_levels,
-                                                        bool blocked)
+                                                        bool blocked, KeyMap xin, KeyMap xout)
 {
     constexpr int TILE = R * NT;
     __shared__ __attribute__((aligned(16))) T S[LdsSkew<T>::size(TILE)];
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int64_t g = tile0 + t + NT * j;
-            Z[t + NT * j] = g < n ? load_elem<T>(kin, vin, g) : Traits<T>::kMax;
+            Z[t + NT * j] = g < n ? map_elem(load_elem<T>(kin, vin, g), xin) : Traits<T>::kMax;
         }
         __syncthreads();
         const LdsSkew<T> W{S, wave * (64 * R) + lane * R};
@@ -55,26 +55,35 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
 #pragma unroll
         for (int j = 0; j < R; ++j)
             v[j] = load_elem<T>(kin, vin, wave0 + 64 * j + lane);
+        if (key_map_on(xin)) {  // wave-uniform
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                v[j] = map_elem(v[j], xin);
+        }
     } else {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int64_t g = wave0 + 64 * j + lane;
-            v[j] = g < n ? load_elem<T>(kin, vin, g) : Traits<T>::kMax;
+            v[j] = g < n ? map_elem(load_elem<T>(kin, vin, g), xin) : Traits<T>::kMax;
         }
     }
 
     sort_tile_core<R, NT, T, NET>(S, v, t, wave_levels, lds_levels);
 
-    if (tile0 + TILE <= n) {
+    if (tile0 + TILE <= n && !key_map_on(xout)) {
 #pragma unroll
         for (int j = 0; j < R; ++j)
             store_elem<T>(kout, vout, tile0 + t + NT * j, Z[t + NT * j]);
+    } else if (tile0 + TILE <= n) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            store_elem<T>(kout, vout, tile0 + t + NT * j, map_elem(Z[t + NT * j], xout));
     } else {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int64_t g = tile0 + t + NT * j;
             if (g < n)
-                store_elem<T>(kout, vout, g, Z[t + NT * j]);
+                store_elem<T>(kout, vout, g, map_elem(Z[t + NT * j], xout));
         }
     }
 }
@@ -82,11 +91,11 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
 template <int R, int NT, typename T, int NET = 0>
 static hipError_t launch_bs(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
                             int64_t n, int wave_levels, int lds_levels, bool blocked,
-                            hipStream_t s)
+                            hipStream_t s, KeyMap xin, KeyMap xout)
 {
     const int64_t tiles = (n + R * NT - 1) / (R * NT);
     hipLaunchKernelGGL((block_sort_kernel<R, NT, T, NET>), dim3((unsigned)tiles), dim3(NT), 0, s, kin,
-                       vin, kout, vout, n, wave_levels, lds_levels, blocked);
+                       vin, kout, vout, n, wave_levels, lds_levels, blocked, xin, xout);
     return hipGetLastError();
 }
 
@@ -101,7 +110,8 @@ bool block_sort_supported(int R, int NT, bool pairs)
 
 hipError_t launch_block_sort(int R, int NT, bool pairs, const int32_t *kin, const int32_t *vin,
                              int32_t *kout, int32_t *vout, int64_t n, int wave_levels,
-                             int lds_levels, bool blocked, hipStream_t s, int net)
+                             int lds_levels, bool blocked, hipStream_t s, int net, KeyMap xin,
+                             KeyMap xout)
 {
     if (net != 0) {  // the 16-input network ablation: keys, R = 16 only
         if (R != 16 || pairs || (net != 1 && net != 2))
@@ -109,9 +119,9 @@ hipError_t launch_block_sort(int R, int NT, bool pairs, const int32_t *kin, cons
 #define HVMS_BSN(NN)                                                                               \
     if (NT == NN)                                                                                  \
         return net == 1 ? launch_bs<16, NN, int32_t, 1>(kin, vin, kout, vout, n, wave_levels,     \
-                                                        lds_levels, blocked, s)                   \
+                                                        lds_levels, blocked, s, xin, xout)                   \
                         : launch_bs<16, NN, int32_t, 2>(kin, vin, kout, vout, n, wave_levels,     \
-                                                        lds_levels, blocked, s);
+                                                        lds_levels, blocked, s, xin, xout);
         HVMS_BSN(256)
         HVMS_BSN(512)
         HVMS_BSN(1024)
@@ -122,9 +132,9 @@ hipError_t launch_block_sort(int R, int NT, bool pairs, const int32_t *kin, cons
     if (R == RR && NT == NN) {                                                                  \
         if (pairs)                                                                              \
             return launch_bs<RR, NN, int64_t>(kin, vin, kout, vout, n, wave_levels, lds_levels, \
-                                              blocked, s);                                               \
-        return launch_bs<RR, NN, int32_t>(kin, vin, kout, vout, n, wave_levels, lds_levels,      \
-                                          blocked, s);                                         \
+                                              blocked, s, xin, xout);                                               \
+        return launch_bs<RR, NN, int32_t>(kin, vin, kout, vout, n, wave_levels, lds_levels, \
+                                          blocked, s, xin, xout);                                         \
     }
     HVMS_BS(16, 256)
     HVMS_BS(16, 512)
@@ -136,7 +146,7 @@ hipError_t launch_block_sort(int R, int NT, bool pairs, const int32_t *kin, cons
     HVMS_BS(32, 512)
     if (R == 32 && NT == 1024 && !pairs)
         return launch_bs<32, 1024, int32_t>(kin, vin, kout, vout, n, wave_levels, lds_levels,
-                                            blocked, s);
+                                            blocked, s, xin, xout);
 #undef HVMS_BS
     return hipErrorInvalidValue;
 }

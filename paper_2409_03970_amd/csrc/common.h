@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hvms_internal.h"
 #include "networks.h"
 
 namespace hvms {
@@ -53,6 +54,21 @@ __device__ __forceinline__ void store_elem(int32_t *__restrict__ k, int32_t *__r
         k[i] = pair_key(x);
         v[i] = pair_val(x);
     }
+}
+
+// Key maps (see KeyMap): the element with its key mapped; pads are never
+// mapped, so the callers apply these to real elements only.
+__device__ __forceinline__ bool key_map_on(KeyMap m) { return (m.um | m.fm) != 0; }
+__device__ __forceinline__ int32_t key_map(int32_t b, KeyMap m)
+{
+    return b ^ (((b >> 31) & m.fm) | m.um);
+}
+template <typename T> __device__ __forceinline__ T map_elem(T x, KeyMap m)
+{
+    if constexpr (sizeof(T) == 4)
+        return key_map(x, m);
+    else
+        return pack_pair(key_map(pair_key(x), m), pair_val(x));
 }
 
 // ---------------------------------------------------------------- comparators

@@ -9,6 +9,15 @@ namespace hvms {
 // abi.hip: the hipError_t reported by hvms_last_hip_error (thread-local)
 void set_last_hip_error(int e);
 
+// Order-preserving map of another 32-bit key type onto int32 order, applied
+// to keys as they are first loaded and again (it is its own inverse) as they
+// are finally stored: key ^ (((key >> 31) & fm) | um).  uint32: um = sign bit;
+// float32: fm = 0x7fffffff (IEEE 754 totalOrder of the bit patterns);
+// int32: both 0 (identity).
+struct KeyMap {
+    int32_t um = 0, fm = 0;
+};
+
 struct CorankOpts {
     int mode;
     int radius_log2;
@@ -20,7 +29,8 @@ struct CorankOpts {
 bool block_sort_supported(int R, int NT, bool pairs);
 hipError_t launch_block_sort(int R, int NT, bool pairs, const int32_t *kin, const int32_t *vin,
                              int32_t *kout, int32_t *vout, int64_t n, int wave_levels,
-                             int lds_levels, bool blocked, hipStream_t s, int net = 0);
+                             int lds_levels, bool blocked, hipStream_t s, int net = 0,
+                             KeyMap xin = {}, KeyMap xout = {});
 
 // merge.hip
 bool merge_tile_supported(int tm, bool pairs);
@@ -32,7 +42,8 @@ hipError_t launch_pass_corank(bool pairs, const int32_t *kin, const int32_t *vin
 // of the persistent grid (0 = as many as fit).
 hipError_t launch_merge_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
                              int32_t *kout, int32_t *vout, int64_t n, int64_t run,
-                             const int64_t *cr, int variant, int occupancy, hipStream_t s);
+                             const int64_t *cr, int variant, int occupancy, hipStream_t s,
+                             KeyMap xout = {});
 int device_cus();
 
 // merge4.hip: four-way passes (sample grid of two-way co-ranks, co-rank
@@ -45,7 +56,7 @@ hipError_t launch_merge4_corank(int tm, bool pairs, const int32_t *kin, const in
                                 const CorankOpts &o, hipStream_t s);
 hipError_t launch_merge4_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
                               int32_t *kout, int32_t *vout, int64_t n, int64_t run,
-                              const void *rec, int occupancy, hipStream_t s);
+                              const void *rec, int occupancy, hipStream_t s, KeyMap xout = {});
 hipError_t launch_corank_list(const int32_t *a, int64_t m, const int32_t *b, int64_t k,
                               const int64_t *diag, int64_t count, int64_t *out,
                               const CorankOpts &o, hipStream_t s);

@@ -76,7 +76,8 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(const int32_t *__restric
                                                         const int32_t *__restrict__ vin,
                                                         int32_t *__restrict__ kout,
                                                         int32_t *__restrict__ vout, int64_t n,
-                                                        int64_t run, const int64_t *__restrict__ cr)
+                                                        int64_t run, const int64_t *__restrict__ cr,
+                                                        KeyMap xout)
 {
     constexpr int TM = NT * VT;
     __shared__ T S[TM];
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(const int32_t *__restric
     for (int k = 0; k < VT; ++k) {
         const int idx = t + NT * k;
         if (idx < cnt)
-            store_elem<T>(kout, vout, o0 + idx, S[idx]);
+            store_elem<T>(kout, vout, o0 + idx, map_elem(S[idx], xout));
     }
 }
 
@@ -136,9 +137,9 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(const int32_t *__restric
 template <int NT, int VT, typename T>
 __global__ __launch_bounds__(NT) void merge_pass_pipe_kernel(PlainMap map, int64_t run,
                                                              const int64_t *__restrict__ cr,
-                                                             int xcd_group)
+                                                             int xcd_group, KeyMap xout)
 {
-    merge_pipe_body<NT, VT, T>(map, run, cr, map.n, xcd_group);
+    merge_pipe_body<NT, VT, T>(map, run, cr, map.n, xcd_group, xout);
 }
 
 // ------------------------------------------------------------- launchers
@@ -194,11 +195,11 @@ bool merge_tile_supported(int tm, bool pairs)
 
 template <int NT, int VT, typename T>
 static hipError_t launch_mp(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
-                            int64_t n, int64_t run, const int64_t *cr, hipStream_t s)
+                            int64_t n, int64_t run, const int64_t *cr, hipStream_t s, KeyMap xout)
 {
     const int64_t ntiles = (n + NT * VT - 1) / (NT * VT);
     hipLaunchKernelGGL((merge_pass_kernel<NT, VT, T>), dim3((unsigned)ntiles), dim3(NT), 0, s,
-                       kin, vin, kout, vout, n, run, cr);
+                       kin, vin, kout, vout, n, run, cr, xout);
     return hipGetLastError();
 }
 
@@ -221,7 +222,7 @@ int device_cus()
 template <int NT, int VT, typename T>
 static hipError_t launch_mpp(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
                              int64_t n, int64_t run, const int64_t *cr, int occupancy, bool xcd,
-                             hipStream_t s)
+                             hipStream_t s, KeyMap xout)
 {
     const int64_t ntiles = (n + NT * VT - 1) / (NT * VT);
     int occ = occupancy;
@@ -244,13 +245,14 @@ static hipError_t launch_mpp(const int32_t *kin, const int32_t *vin, int32_t *ko
     map.n = n;
     map.ntiles = ntiles;
     hipLaunchKernelGGL((merge_pass_pipe_kernel<NT, VT, T>), dim3((unsigned)grid), dim3(NT), 0, s,
-                       map, run, cr, xcd ? 1 : 0);
+                       map, run, cr, xcd ? 1 : 0, xout);
     return hipGetLastError();
 }
 
 hipError_t launch_merge_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
                              int32_t *kout, int32_t *vout, int64_t n, int64_t run,
-                             const int64_t *cr, int variant, int occupancy, hipStream_t s)
+                             const int64_t *cr, int variant, int occupancy, hipStream_t s,
+                             KeyMap xout)
 {
     // The pipelined kernel moves 16-byte chunks: it needs 16-byte aligned
     // arrays and at least 16 elements; anything else takes the simple kernel.
@@ -260,34 +262,34 @@ hipError_t launch_merge_pass(int tm, bool pairs, const int32_t *kin, const int32
         const bool xcd = variant == 3;
         switch (tm) {
         case 2048:
-            return pairs ? launch_mpp<256, 8, int64_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s)
-                         : launch_mpp<256, 8, int32_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s);
+            return pairs ? launch_mpp<256, 8, int64_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s, xout)
+                         : launch_mpp<256, 8, int32_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s, xout);
         case 4096:
-            return pairs ? launch_mpp<256, 16, int64_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s)
-                         : launch_mpp<256, 16, int32_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s);
+            return pairs ? launch_mpp<256, 16, int64_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s, xout)
+                         : launch_mpp<256, 16, int32_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s, xout);
         case 8192:
-            return pairs ? launch_mpp<512, 16, int64_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s)
-                         : launch_mpp<512, 16, int32_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s);
+            return pairs ? launch_mpp<512, 16, int64_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s, xout)
+                         : launch_mpp<512, 16, int32_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s, xout);
         case 16384:
             if (!pairs)
-                return launch_mpp<512, 32, int32_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s);
+                return launch_mpp<512, 32, int32_t>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s, xout);
             break;
         }
         return hipErrorInvalidValue;
     }
     switch (tm) {
     case 2048:
-        return pairs ? launch_mp<256, 8, int64_t>(kin, vin, kout, vout, n, run, cr, s)
-                     : launch_mp<256, 8, int32_t>(kin, vin, kout, vout, n, run, cr, s);
+        return pairs ? launch_mp<256, 8, int64_t>(kin, vin, kout, vout, n, run, cr, s, xout)
+                     : launch_mp<256, 8, int32_t>(kin, vin, kout, vout, n, run, cr, s, xout);
     case 4096:
-        return pairs ? launch_mp<256, 16, int64_t>(kin, vin, kout, vout, n, run, cr, s)
-                     : launch_mp<256, 16, int32_t>(kin, vin, kout, vout, n, run, cr, s);
+        return pairs ? launch_mp<256, 16, int64_t>(kin, vin, kout, vout, n, run, cr, s, xout)
+                     : launch_mp<256, 16, int32_t>(kin, vin, kout, vout, n, run, cr, s, xout);
     case 8192:
-        return pairs ? launch_mp<512, 16, int64_t>(kin, vin, kout, vout, n, run, cr, s)
-                     : launch_mp<512, 16, int32_t>(kin, vin, kout, vout, n, run, cr, s);
+        return pairs ? launch_mp<512, 16, int64_t>(kin, vin, kout, vout, n, run, cr, s, xout)
+                     : launch_mp<512, 16, int32_t>(kin, vin, kout, vout, n, run, cr, s, xout);
     case 16384:
         if (!pairs)
-            return launch_mp<512, 32, int32_t>(kin, vin, kout, vout, n, run, cr, s);
+            return launch_mp<512, 32, int32_t>(kin, vin, kout, vout, n, run, cr, s, xout);
         break;
     }
     return hipErrorInvalidValue;

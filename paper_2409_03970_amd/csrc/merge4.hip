@@ -315,7 +315,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
                                                          int32_t *__restrict__ kout,
                                                          int32_t *__restrict__ vout, int64_t n,
                                                          int64_t run, const Quad *__restrict__ rec,
-                                                         int64_t ntiles)
+                                                         int64_t ntiles, KeyMap xout)
 {
     constexpr int TM = NT * VT;
     constexpr int CH = VT / 4 + 1;  // chunk slots per thread: TM/4 + 6 chunks at most
@@ -447,6 +447,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
         const int i = lds_corank(MX, nxw, nxw, nyw, diag);
         T out[VT];
         reg_merge<VT>(MX, nxw, nxw, nyw, i, diag - i, out);
+        if (key_map_on(xout)) {  // wave-uniform: the last pass of a uint32 / float32 sort
+#pragma unroll
+            for (int k = 0; k < VT; ++k)
+                out[k] = map_elem(out[k], xout);
+        }
         lds_barrier();
         // stage the rows in M (skewed, 16-byte stores), then copy out
         // coalesced; a tile starts at a multiple of TM, so 16-byte aligned
@@ -482,7 +487,8 @@ static hipError_t launch_quad_corank(const int32_t *kin, const int32_t *vin, int
 
 template <int NT, int VT, typename T>
 static hipError_t launch_m4(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
-                            int64_t n, int64_t run, const void *rec, int occupancy, hipStream_t s)
+                            int64_t n, int64_t run, const void *rec, int occupancy, hipStream_t s,
+                            KeyMap xout)
 {
     const int64_t ntiles = (n + NT * VT - 1) / (NT * VT);
     int occ = occupancy;
@@ -495,7 +501,7 @@ static hipError_t launch_m4(const int32_t *kin, const int32_t *vin, int32_t *kou
     if (grid > ntiles)
         grid = ntiles;
     hipLaunchKernelGGL((merge4_pipe_kernel<NT, VT, T>), dim3((unsigned)grid), dim3(NT), 0, s, kin,
-                       vin, kout, vout, n, run, (const Quad *)rec, ntiles);
+                       vin, kout, vout, n, run, (const Quad *)rec, ntiles, xout);
     return hipGetLastError();
 }
 
@@ -516,18 +522,18 @@ hipError_t launch_merge4_corank(int tm, bool pairs, const int32_t *kin, const in
 
 hipError_t launch_merge4_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
                               int32_t *kout, int32_t *vout, int64_t n, int64_t run,
-                              const void *rec, int occupancy, hipStream_t s)
+                              const void *rec, int occupancy, hipStream_t s, KeyMap xout)
 {
     switch (tm) {
     case 2048:
-        return pairs ? launch_m4<256, 8, int64_t>(kin, vin, kout, vout, n, run, rec, occupancy, s)
+        return pairs ? launch_m4<256, 8, int64_t>(kin, vin, kout, vout, n, run, rec, occupancy, s, xout)
                      : hipErrorInvalidValue;
     case 4096:
-        return pairs ? launch_m4<256, 16, int64_t>(kin, vin, kout, vout, n, run, rec, occupancy, s)
-                     : launch_m4<256, 16, int32_t>(kin, vin, kout, vout, n, run, rec, occupancy, s);
+        return pairs ? launch_m4<256, 16, int64_t>(kin, vin, kout, vout, n, run, rec, occupancy, s, xout)
+                     : launch_m4<256, 16, int32_t>(kin, vin, kout, vout, n, run, rec, occupancy, s, xout);
     case 8192:
         return pairs ? hipErrorInvalidValue
-                     : launch_m4<512, 16, int32_t>(kin, vin, kout, vout, n, run, rec, occupancy, s);
+                     : launch_m4<512, 16, int32_t>(kin, vin, kout, vout, n, run, rec, occupancy, s, xout);
     }
     return hipErrorInvalidValue;
 }

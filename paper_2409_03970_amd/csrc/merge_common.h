@@ -375,17 +375,18 @@ __device__ __forceinline__ void copy_out(const LdsSkew<T> &W, int32_t *__restric
             continue;
         const int64_t e = abs0 + 4 * c;
         if (4 * c + 4 <= cnt) {
-            T x[4];
-#pragma unroll
-            for (int h = 0; h < 4; h += E) {
-                const Vec y = *(const Vec *)&W[4 * c + h];
-#pragma unroll
-                for (int u = 0; u < E; ++u)
-                    x[h + u] = y[u];
-            }
             if constexpr (sizeof(T) == 4) {
-                *(int4 *)(k + e) = make_int4(x[0], x[1], x[2], x[3]);
+                // one 16-byte copy (W[4c] is 16-byte aligned in the skewed layout)
+                *(int4 *)(k + e) = *(const int4 *)&W[4 * c];
             } else {
+                T x[4];
+#pragma unroll
+                for (int h = 0; h < 4; h += E) {
+                    const Vec y = *(const Vec *)&W[4 * c + h];
+#pragma unroll
+                    for (int u = 0; u < E; ++u)
+                        x[h + u] = y[u];
+                }
                 *(int4 *)(k + e) =
                     make_int4(pair_key(x[0]), pair_key(x[1]), pair_key(x[2]), pair_key(x[3]));
                 *(int4 *)(v + e) =
@@ -403,7 +404,7 @@ __device__ __forceinline__ void copy_out(const LdsSkew<T> &W, int32_t *__restric
 template <int NT, int VT, typename T, typename Map>
 __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
                                                 const int64_t *__restrict__ cr, int64_t n_abs,
-                                                int xcd_group)
+                                                int xcd_group, KeyMap xout = {})
 {
     constexpr int TM = NT * VT;
     constexpr int CH = VT / 4 + 1;  // chunk slots per thread: TM/4 + 3 chunks at most
@@ -501,6 +502,16 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
         const int i = lds_corank(A, cur.acnt, boff, cur.bcnt, diag);
         T out[VT];
         serial_merge<VT>(A, cur.acnt, boff, cur.bcnt, i, diag - i, out);
+        // the last pass of a uint32 / float32 sort maps the keys back: keys in
+        // registers here, pairs where the packed pairs are split for the
+        // store (each keeps the 16-byte stores and the register budget)
+        if constexpr (sizeof(T) == 4) {
+            if (key_map_on(xout)) {  // wave-uniform
+#pragma unroll
+                for (int k = 0; k < VT; ++k)
+                    out[k] = map_elem(out[k], xout);
+            }
+        }
         lds_barrier();
 #pragma unroll
         for (int k = 0; k < VT; ++k)
@@ -522,16 +533,21 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
                     *(int4 *)(cur.r.ok + e) = *(const int4 *)(S + 4 * c);
                 } else {
                     const T x0 = S[4 * c], x1 = S[4 * c + 1], x2 = S[4 * c + 2], x3 = S[4 * c + 3];
-                    *(int4 *)(cur.r.ok + e) =
-                        make_int4(pair_key(x0), pair_key(x1), pair_key(x2), pair_key(x3));
+                    int4 kk = make_int4(pair_key(x0), pair_key(x1), pair_key(x2), pair_key(x3));
                     *(int4 *)(cur.r.ov + e) =
                         make_int4(pair_val(x0), pair_val(x1), pair_val(x2), pair_val(x3));
+                    if (key_map_on(xout))  // wave-uniform
+                        kk = make_int4(key_map(kk.x, xout), key_map(kk.y, xout),
+                                       key_map(kk.z, xout), key_map(kk.w, xout));
+                    *(int4 *)(cur.r.ok + e) = kk;
                 }
             } else {
 #pragma unroll
                 for (int q2 = 0; q2 < 4; ++q2)
                     if (4 * c + q2 >= cur.shift && 4 * c + q2 < end)
-                        store_elem<T>(cur.r.ok, cur.r.ov, e + q2, S[4 * c + q2]);
+                        store_elem<T>(cur.r.ok, cur.r.ov, e + q2,
+                                      sizeof(T) == 8 ? map_elem(S[4 * c + q2], xout)
+                                                     : S[4 * c + q2]);
             }
         }
         if (!more)

@@ -26,7 +26,7 @@ def _declared():
 
 def test_every_declared_symbol_is_exported():
     names = _declared()
-    assert len(names) == 19
+    assert len(names) == 23
     L = hv.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -76,6 +76,14 @@ def test_argument_errors_before_any_launch():
     learned_without_model = hv.Options(corank_mode=1)
     assert L.hvms_sort_i32(FAKE, FAKE, 10, None, 0, None, ctypes.byref(learned_without_model)) == -1
     assert L.hvms_sort_pairs_i32(FAKE, None, FAKE, FAKE, 3, None, 0, None, None) == -1
+    for f in (L.hvms_sort_u32, L.hvms_sort_f32):
+        assert f(None, FAKE, 5, None, 0, None, None) == -1
+        assert f(FAKE, FAKE, 0, None, 0, None, None) == 0
+        assert f(FAKE, FAKE, 1 << 20, None, 0, None, None) == -2
+        assert f(FAKE, FAKE, 10, None, 0, None, ctypes.byref(bad)) == -4
+    for f in (L.hvms_sort_pairs_u32, L.hvms_sort_pairs_f32):
+        assert f(FAKE, None, FAKE, FAKE, 3, None, 0, None, None) == -1
+        assert f(FAKE, FAKE, FAKE, FAKE, 1 << 20, FAKE, 16, None, None) == -2
     assert L.hvms_sort_runs_i32(FAKE, FAKE, 100, 2, None, None) == -1        # run below R
     assert L.hvms_sort_runs_i32(FAKE, FAKE, 100, 20, None, None) == -1       # run above tile
     assert L.hvms_merge_pass_i32(FAKE, FAKE, 100, 3000, None, 0, None, None) == -1  # not 2^k
