@@ -124,6 +124,34 @@ def four_way_bench(x, ref_out, opts):
             "block_sort_ms": round(ev[0].elapsed_time(ev[1]), 3), "equal_to_two_way": equal}
 
 
+def key_types_bench(n):
+    """uint32 and float32 keys (tuned sort options) against int32 on the
+    same number of keys; the key map is fused into the first and last
+    launches, so the rates should match."""
+    dev = torch.device("cuda", 0)
+    from paper_2409_03970_amd import tune
+    opts = tune.tuned_options("sort", n) or {}
+    ws = hv._workspace(hv.lib().hvms_sort_workspace_bytes(n, 0, hv._opts(opts)), dev)
+    g = torch.Generator(device=dev).manual_seed(0)
+    res = {}
+    bits = torch.randint(-2**31, 2**31 - 1, (n,), dtype=torch.int32, device=dev, generator=g)
+    out = torch.empty_like(bits)
+    cases = (("int32", bits, out, hv.hvms_sort_i32),
+             ("uint32", bits.view(torch.uint32), out.view(torch.uint32), hv.hvms_sort_u32))
+    for name, x, y, fn in cases:
+        ms = _median_ms(lambda: fn(x, y, ws, opts=opts))
+        mono = out ^ (-2**31) if name == "uint32" else out   # unsigned order as signed
+        res[name] = {"ms": round(ms, 3), "gkeys_per_s": round(n / ms / 1e6, 3),
+                     "sorted": bool((mono[1:] >= mono[:-1]).all())}
+    f = torch.randn(n, device=dev, generator=g) * 1e3
+    f[f == 0] = 1.0
+    fo = torch.empty_like(f)
+    ms = _median_ms(lambda: hv.hvms_sort_f32(f, fo, ws, opts=opts))
+    res["float32"] = {"ms": round(ms, 3), "gkeys_per_s": round(n / ms / 1e6, 3),
+                      "sorted": bool((fo[1:] >= fo[:-1]).all())}
+    return res
+
+
 def _median_ms(fn, reps=3):
     fn()
     torch.cuda.synchronize()
@@ -553,6 +581,11 @@ def main():
             rec["corank_modes_2p28"] = corank_modes(xs, dists, out, ws, opts)
         except Exception as e:  # an extra must never cost the headline line
             rec["corank_modes_2p28"] = {"error": repr(e)}
+        log("key_types_2p28")
+        try:
+            rec["key_types_2p28"] = key_types_bench(n)
+        except Exception as e:
+            rec["key_types_2p28"] = {"error": repr(e)}
         log("four_way_2p28")
         try:
             hv.hvms_sort_i32(xs[0], out, ws, opts=opts)
