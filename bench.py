@@ -152,6 +152,36 @@ def key_types_bench(n):
     return res
 
 
+def merge_table3_bench(n):
+    """Table 3 analog: the two per-thread mergers of a merge pass -- serial
+    (the serial part of the hybrid merger) and the bitonic network in
+    registers -- at VT = 8, 16 and 32 outputs per thread (merge tiles 2048,
+    8192, 16384), on one pass over 2^28 uniform keys in sorted runs of
+    16,384.  Times the whole pass (co-rank kernel + merge kernel)."""
+    dev = torch.device("cuda", 0)
+    base = {"keys_per_lane": 32, "block_threads": 512}
+    res = {}
+    for dist in ("uniform", "sorted", "distinct16"):
+        x = inputs.keys(n, dist, seed=3, device=dev)
+        runs = hv.sort_runs(x, 14, opts=base)
+        del x
+        out = torch.empty_like(runs)
+        ref = None
+        for tm, vt in ((2048, 8), (8192, 16), (16384, 32)):
+            for name, var in (("serial", 2), ("bitonic", 4)):
+                o = dict(base, merge_tile=tm, merge_variant=var)
+                ws = hv._workspace(hv.lib().hvms_merge_workspace_bytes(n, 16384, hv._opts(o)), dev)
+                ms = _median_ms(lambda: hv.hvms_merge_pass_i32(runs, out, 16384, ws, opts=o))
+                if ref is None:
+                    ref = out.clone()
+                res[f"{dist}_2x{vt}_{name}"] = {
+                    "ms": round(ms, 4), "gbs": round(8.0 * n / (ms / 1e3) / 1e9, 1),
+                    "equal": bool(torch.equal(out, ref))}
+        del runs, out, ref
+        torch.cuda.empty_cache()
+    return res
+
+
 def _median_ms(fn, reps=3):
     fn()
     torch.cuda.synchronize()
@@ -595,6 +625,7 @@ def main():
         del xs, out, ws, ev_sets
         torch.cuda.empty_cache()
         extras = (("in_register_sort_table2", table2_bench),
+                  ("merge_table3", lambda: merge_table3_bench(n)),
                   ("pairs_2p28", lambda: pairs_bench(n)),
                   ("batched_learned_pairs_50k_segments", config5_bench if args.all else None),
                   ("batched_200k_segments", batched_bench),

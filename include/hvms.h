@@ -70,7 +70,10 @@ enum {
  *                   the co-rank kernels add to (see HVMS_STAT_*), or NULL.
  *   merge_variant   global merge kernel: 0 default, 1 one tile per workgroup,
  *                   2 persistent with the next tile prefetched during the
- *                   merge, 3 as 2 with each XCD walking contiguous tiles.
+ *                   merge, 3 as 2 with each XCD walking contiguous tiles,
+ *                   4 as 2 with each thread's share merged by the bitonic
+ *                   network in registers instead of serially (plain key
+ *                   sorts only; the two mergers of Table 3).
  *   merge_occupancy workgroups per CU in the persistent grid (0 = all that fit).
  *   merge_ways      2: two-way merge passes (one merge level per pass); 4:
  *                   four-way passes that do two levels per trip through HBM

@@ -65,8 +65,10 @@ int resolve(const hvms_options *o, bool pairs, Cfg &c)
         return c.net < 0 || c.net > 2 ? HVMS_ERR_INVALID_ARG : HVMS_ERR_UNSUPPORTED;
     c.variant = o ? o->merge_variant : 0;
     c.occupancy = o ? o->merge_occupancy : 0;
-    if (c.variant < 0 || c.variant > 3 || c.occupancy < 0 || c.occupancy > 32)
+    if (c.variant < 0 || c.variant > 4 || c.occupancy < 0 || c.occupancy > 32)
         return HVMS_ERR_INVALID_ARG;
+    if (c.variant == 4 && pairs)  // the bitonic register merge is built for keys
+        return HVMS_ERR_UNSUPPORTED;
     c.co.mode = o ? o->corank_mode : HVMS_CORANK_BINARY;
     c.co.radius_log2 = (o && o->radius_log2) ? o->radius_log2 : 12;
     c.co.cdf = o ? o->cdf_params : nullptr;
@@ -469,6 +471,8 @@ static int run_segmented(const int32_t *kin, const int32_t *vin, int32_t *kout, 
     a.NT = c.NT;
     a.K = c.K;
     a.TM = c.TM;
+    if (c.variant == 4)
+        return HVMS_ERR_UNSUPPORTED;
     a.variant = c.variant;
     a.occupancy = c.occupancy;
     a.co = c.co;

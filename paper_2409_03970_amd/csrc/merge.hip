@@ -134,12 +134,12 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(const int32_t *__restric
 
 // ------------------------------------------- persistent, pipelined merge pass
 
-template <int NT, int VT, typename T>
+template <int NT, int VT, typename T, bool BIT = false>
 __global__ __launch_bounds__(NT) void merge_pass_pipe_kernel(PlainMap map, int64_t run,
                                                              const int64_t *__restrict__ cr,
                                                              int xcd_group, KeyMap xout)
 {
-    merge_pipe_body<NT, VT, T>(map, run, cr, map.n, xcd_group, xout);
+    merge_pipe_body<NT, VT, T, PlainMap, BIT>(map, run, cr, map.n, xcd_group, xout);
 }
 
 // ------------------------------------------------------------- launchers
@@ -219,7 +219,7 @@ int device_cus()
     return cus[dev];
 }
 
-template <int NT, int VT, typename T>
+template <int NT, int VT, typename T, bool BIT = false>
 static hipError_t launch_mpp(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
                              int64_t n, int64_t run, const int64_t *cr, int occupancy, bool xcd,
                              hipStream_t s, KeyMap xout)
@@ -228,7 +228,7 @@ static hipError_t launch_mpp(const int32_t *kin, const int32_t *vin, int32_t *ko
     int occ = occupancy;
     if (occ <= 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &occ, (const void *)merge_pass_pipe_kernel<NT, VT, T>, NT, 0) != hipSuccess ||
+                &occ, (const void *)merge_pass_pipe_kernel<NT, VT, T, BIT>, NT, 0) != hipSuccess ||
             occ <= 0)
             occ = 1;
     }
@@ -244,7 +244,7 @@ static hipError_t launch_mpp(const int32_t *kin, const int32_t *vin, int32_t *ko
     map.ov = vout;
     map.n = n;
     map.ntiles = ntiles;
-    hipLaunchKernelGGL((merge_pass_pipe_kernel<NT, VT, T>), dim3((unsigned)grid), dim3(NT), 0, s,
+    hipLaunchKernelGGL((merge_pass_pipe_kernel<NT, VT, T, BIT>), dim3((unsigned)grid), dim3(NT), 0, s,
                        map, run, cr, xcd ? 1 : 0, xout);
     return hipGetLastError();
 }
@@ -258,6 +258,19 @@ hipError_t launch_merge_pass(int tm, bool pairs, const int32_t *kin, const int32
     // arrays and at least 16 elements; anything else takes the simple kernel.
     const bool aligned = ((uintptr_t)kin % 16 == 0) && ((uintptr_t)kout % 16 == 0) &&
                          (!pairs || (((uintptr_t)vin % 16 == 0) && ((uintptr_t)vout % 16 == 0)));
+    if (variant == 4 && !pairs && aligned && n >= 16) {  // bitonic register merge (keys)
+        switch (tm) {
+        case 2048:
+            return launch_mpp<256, 8, int32_t, true>(kin, vin, kout, vout, n, run, cr, occupancy, false, s, xout);
+        case 4096:
+            return launch_mpp<256, 16, int32_t, true>(kin, vin, kout, vout, n, run, cr, occupancy, false, s, xout);
+        case 8192:
+            return launch_mpp<512, 16, int32_t, true>(kin, vin, kout, vout, n, run, cr, occupancy, false, s, xout);
+        case 16384:
+            return launch_mpp<512, 32, int32_t, true>(kin, vin, kout, vout, n, run, cr, occupancy, false, s, xout);
+        }
+        return hipErrorInvalidValue;
+    }
     if (variant != 1 && aligned && n >= 16) {
         const bool xcd = variant == 3;
         switch (tm) {

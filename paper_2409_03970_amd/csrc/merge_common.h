@@ -401,14 +401,19 @@ __device__ __forceinline__ void copy_out(const LdsSkew<T> &W, int32_t *__restric
     }
 }
 
-template <int NT, int VT, typename T, typename Map>
+// BIT: each thread merges its merge-path share with the bitonic network in
+// registers (reg_merge) instead of the serial merge (the two mergers of
+// Table 3; the serial one is the default).
+template <int NT, int VT, typename T, typename Map, bool BIT = false>
 __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
                                                 const int64_t *__restrict__ cr, int64_t n_abs,
                                                 int xcd_group, KeyMap xout = {})
 {
     constexpr int TM = NT * VT;
     constexpr int CH = VT / 4 + 1;  // chunk slots per thread: TM/4 + 3 chunks at most
-    __shared__ __attribute__((aligned(16))) T S[TM + 16];
+    // the windows: TM elements plus up to 6 of chunk alignment (plus VT - 1
+    // read past a window's end by reg_merge)
+    __shared__ __attribute__((aligned(16))) T S[TM + 16 + (BIT ? VT : 0)];
     const int t = threadIdx.x;
     const int64_t ntiles = map.count();
 
@@ -501,7 +506,10 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
         const int diag = t * VT < cur.cnt ? t * VT : cur.cnt;
         const int i = lds_corank(A, cur.acnt, boff, cur.bcnt, diag);
         T out[VT];
-        serial_merge<VT>(A, cur.acnt, boff, cur.bcnt, i, diag - i, out);
+        if constexpr (BIT)
+            reg_merge<VT>(A, cur.acnt, boff, cur.bcnt, i, diag - i, out);
+        else
+            serial_merge<VT>(A, cur.acnt, boff, cur.bcnt, i, diag - i, out);
         // the last pass of a uint32 / float32 sort maps the keys back: keys in
         // registers here, pairs where the packed pairs are split for the
         // store (each keeps the 16-byte stores and the register budget)

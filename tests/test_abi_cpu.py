@@ -73,6 +73,10 @@ def test_argument_errors_before_any_launch():
     assert L.hvms_sort_i32(FAKE, FAKE, 1 << 20, ctypes.c_void_p(0x100004), 1 << 30, None, None) == -2
     bad = hv.Options(block_threads=300)
     assert L.hvms_sort_i32(FAKE, FAKE, 10, None, 0, None, ctypes.byref(bad)) == -4
+    v4 = hv.Options(merge_variant=4)
+    assert L.hvms_sort_i32(FAKE, FAKE, 1 << 20, None, 0, None, ctypes.byref(v4)) == -2  # accepted
+    assert L.hvms_sort_pairs_i32(FAKE, FAKE, FAKE, FAKE, 10, None, 0, None, ctypes.byref(v4)) == -4
+    assert L.hvms_sort_i32(FAKE, FAKE, 10, None, 0, None, ctypes.byref(hv.Options(merge_variant=5))) == -1
     learned_without_model = hv.Options(corank_mode=1)
     assert L.hvms_sort_i32(FAKE, FAKE, 10, None, 0, None, ctypes.byref(learned_without_model)) == -1
     assert L.hvms_sort_pairs_i32(FAKE, None, FAKE, FAKE, 3, None, 0, None, None) == -1

@@ -210,6 +210,34 @@ def test_merge_pass_matches_oracle(run, n_runs):
     assert np.array_equal(y, want)
 
 
+@pytest.mark.parametrize("tm", [2048, 4096, 8192, 16384])
+@pytest.mark.parametrize("variant", [2, 4])
+@pytest.mark.parametrize("dist", ["uniform", "distinct16", "sorted"])
+def test_merge_pass_serial_and_bitonic_mergers(tm, variant, dist):
+    # the two per-thread mergers (serial, bitonic network in registers) at
+    # VT = 8, 16, 16, 32 outputs per thread, ragged last pair
+    run = 16384
+    n = 5 * run + 4321
+    x = inputs.keys(n, dist, seed=tm + variant, device=DEV).cpu().numpy()
+    offs = np.append(np.arange(0, n, run), n)
+    runs = oracle.segmented_sort(x, offs)
+    y = hv.merge_pass(torch.from_numpy(runs).to(DEV), run,
+                      opts={"merge_tile": tm, "merge_variant": variant,
+                            "keys_per_lane": 32, "block_threads": 512}).cpu().numpy()
+    want = np.concatenate([oracle.merge(runs[a:min(a + run, n)], runs[min(a + run, n):min(a + 2 * run, n)])
+                           for a in range(0, n, 2 * run)])
+    assert np.array_equal(y, want)
+
+
+@pytest.mark.parametrize("tm", [2048, 8192, 16384])
+def test_sort_with_bitonic_merger(tm):
+    n = 3 * 16384 * 8 + 77
+    x = inputs.keys(n, "zipf", seed=tm, device=DEV)
+    y = hv.sort(x, opts={"keys_per_lane": 32, "block_threads": 512, "merge_tile": tm,
+                         "merge_variant": 4})
+    assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy()))
+
+
 @pytest.mark.parametrize("mode", [hv.CORANK_BINARY, hv.CORANK_LINEAR])
 @pytest.mark.parametrize("seed", range(6))
 def test_corank_all_diagonals_match_oracle(mode, seed):
@@ -257,6 +285,23 @@ def test_full_size_2pow28(dist):
     x = inputs.keys(n, dist, seed=0, device=DEV)
     y = hv.sort(x)
     torch.cuda.synchronize()
+    _full_check(x, y)
+
+
+@pytest.mark.parametrize("ways", [2, 4])
+def test_beyond_2pow31_keys(ways):
+    # more keys than a 32-bit index reaches (8.6 GB), ragged: every index,
+    # tile count and co-rank path must be 64-bit
+    n = (1 << 31) + 1003
+    _say("beyond 2^31, ways", ways)
+    x = inputs.keys(n, "uniform", seed=31, device=DEV)
+    opts = {"keys_per_lane": 32, "block_threads": 512, "merge_tile": 8192, "merge_ways": ways}
+    y = hv.sort(x, opts=opts)
+    torch.cuda.synchronize()
+    assert bool((y[1:] >= y[:-1]).all())
+    del x
+    torch.cuda.empty_cache()
+    x = inputs.keys(n, "uniform", seed=31, device=DEV)   # the same input again
     _full_check(x, y)
 
 
