@@ -135,9 +135,9 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(const int32_t *__restric
 // ------------------------------------------- persistent, pipelined merge pass
 
 template <int NT, int VT, typename T, bool BIT = false>
-__global__ __launch_bounds__(NT) void merge_pass_pipe_kernel(PlainMap map, int64_t run,
-                                                             const int64_t *__restrict__ cr,
-                                                             int xcd_group, KeyMap xout)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(merge_waves_per_simd<T, VT>())))
+void merge_pass_pipe_kernel(PlainMap map, int64_t run, const int64_t *__restrict__ cr,
+                            int xcd_group, KeyMap xout)
 {
     merge_pipe_body<NT, VT, T, PlainMap, BIT>(map, run, cr, map.n, xcd_group, xout);
 }

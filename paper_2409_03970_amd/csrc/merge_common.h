@@ -5,6 +5,8 @@
 // all parameterised by a tile map that says where each output tile lives.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 #include "mlp_common.h"
 
@@ -401,6 +403,15 @@ __device__ __forceinline__ void copy_out(const LdsSkew<T> &W, int32_t *__restric
     }
 }
 
+// Register targets of the merge kernels: waves per SIMD that they fit
+// without spilling (keys 4, or 2 at VT = 32; pairs 3).  A register over an
+// allocation step costs a whole wave, so the target is stated, not left to
+// the allocator.
+template <typename T, int VT> constexpr int merge_waves_per_simd()
+{
+    return sizeof(T) == 8 ? 3 : (VT <= 16 ? 4 : 2);
+}
+
 // BIT: each thread merges its merge-path share with the bitonic network in
 // registers (reg_merge) instead of the serial merge (the two mergers of
 // Table 3; the serial one is the default).
@@ -411,9 +422,17 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
 {
     constexpr int TM = NT * VT;
     constexpr int CH = VT / 4 + 1;  // chunk slots per thread: TM/4 + 3 chunks at most
-    // the windows: TM elements plus up to 6 of chunk alignment (plus VT - 1
-    // read past a window's end by reg_merge)
-    __shared__ __attribute__((aligned(16))) T S[TM + 16 + (BIT ? VT : 0)];
+    // The windows: TM elements plus up to 6 of chunk alignment (plus VT - 1
+    // read past a window's end by reg_merge), in the skewed layout: threads
+    // whose shares lie VT apart (runs of equal keys, presorted input) then
+    // hit 4-way instead of 16-way bank conflicts, and 16-byte chunks stay
+    // aligned.  At VT = 32 the padding would cost the second workgroup per
+    // CU, so that tile stays plain.
+    constexpr bool SKEW = VT <= 16;
+    using View = std::conditional_t<SKEW, LdsSkew<T>, LdsPlain<T>>;
+    constexpr int SN = TM + 16 + (BIT ? VT : 0);
+    __shared__ __attribute__((aligned(16))) T S[SKEW ? LdsSkew<T>::size(SN) : SN];
+    const View Z{S, 0};
     const int t = threadIdx.x;
     const int64_t ntiles = map.count();
 
@@ -487,7 +506,7 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
             if (c < cur.nA + cur.nB) {
                 if (has_tail && chunk_elem(cur, c) == e_tail)
                     fix_tail<T>(pf[q], cur.r.ik, cur.r.iv, e_tail, n_abs);
-                put_chunk<T>(S, c, pf[q]);
+                put_chunk<T>(&Z[4 * c], 0, pf[q]);
             }
         }
         lds_barrier();
@@ -501,7 +520,7 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
             crn = gn + step < last ? load_cr(gn + step) : 0;
         }
 
-        const LdsPlain<T> A{S, cur.a_off};
+        const View A{S, cur.a_off};
         const int boff = cur.b_base - cur.a_off;
         const int diag = t * VT < cur.cnt ? t * VT : cur.cnt;
         const int i = lds_corank(A, cur.acnt, boff, cur.bcnt, diag);
@@ -523,7 +542,7 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
         lds_barrier();
 #pragma unroll
         for (int k = 0; k < VT; ++k)
-            S[cur.shift + t * VT + k] = out[k];
+            Z[cur.shift + t * VT + k] = out[k];
         lds_barrier();
 
         // LDS index x holds output x - shift, i.e. absolute index
@@ -538,9 +557,9 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
             const int64_t e = abs0 + 4 * c;
             if (4 * c >= cur.shift && 4 * c + 4 <= end) {
                 if constexpr (sizeof(T) == 4) {
-                    *(int4 *)(cur.r.ok + e) = *(const int4 *)(S + 4 * c);
+                    *(int4 *)(cur.r.ok + e) = *(const int4 *)&Z[4 * c];
                 } else {
-                    const T x0 = S[4 * c], x1 = S[4 * c + 1], x2 = S[4 * c + 2], x3 = S[4 * c + 3];
+                    const T x0 = Z[4 * c], x1 = Z[4 * c + 1], x2 = Z[4 * c + 2], x3 = Z[4 * c + 3];
                     int4 kk = make_int4(pair_key(x0), pair_key(x1), pair_key(x2), pair_key(x3));
                     *(int4 *)(cur.r.ov + e) =
                         make_int4(pair_val(x0), pair_val(x1), pair_val(x2), pair_val(x3));
@@ -554,8 +573,8 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
                 for (int q2 = 0; q2 < 4; ++q2)
                     if (4 * c + q2 >= cur.shift && 4 * c + q2 < end)
                         store_elem<T>(cur.r.ok, cur.r.ov, e + q2,
-                                      sizeof(T) == 8 ? map_elem(S[4 * c + q2], xout)
-                                                     : S[4 * c + q2]);
+                                      sizeof(T) == 8 ? map_elem(Z[4 * c + q2], xout)
+                                                     : Z[4 * c + q2]);
             }
         }
         if (!more)

@@ -314,7 +314,8 @@ __global__ __launch_bounds__(256) void seg_corank_kernel(SegMap map, int64_t run
 }
 
 template <int NT, int VT, typename T>
-__global__ __launch_bounds__(NT) void seg_merge_kernel(SegMap map, int64_t run,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(merge_waves_per_simd<T, VT>())))
+void seg_merge_kernel(SegMap map, int64_t run,
                                                        const int64_t *__restrict__ cr,
                                                        int64_t n_abs, int xcd_group)
 {
