@@ -36,20 +36,28 @@ WORKLOADS = {
 }
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "merge_pass_counters_sort_2p28_six.md")
-KERNEL_SOURCES = ("paper_2409_03970_amd/csrc/merge_common.h", "paper_2409_03970_amd/csrc/merge.hip",
-                  "paper_2409_03970_amd/csrc/common.h")
+# committed counter summaries per merge kernel (two-way, four-way) and the
+# sources whose hash they record
+COUNTERS = {
+    2: (os.path.join(ROOT, "profiles", "merge_pass_counters_sort_2p28_six.md"),
+        ("paper_2409_03970_amd/csrc/merge_common.h", "paper_2409_03970_amd/csrc/merge.hip",
+         "paper_2409_03970_amd/csrc/common.h")),
+    4: (os.path.join(ROOT, "profiles", "merge4_pass_counters_sort_2p28_six.md"),
+        ("paper_2409_03970_amd/csrc/merge_common.h", "paper_2409_03970_amd/csrc/merge4.hip",
+         "paper_2409_03970_amd/csrc/common.h")),
+}
 
 
-def counter_traffic():
-    """HBM bytes per merge-pass launch from the committed FETCH_SIZE /
-    WRITE_SIZE runs, or None once the kernel sources differ from the ones
+def counter_traffic(ways=2):
+    """HBM bytes per merge launch from the committed FETCH_SIZE / WRITE_SIZE
+    runs of that merge kernel, or None once its sources differ from the ones
     the counters were taken on."""
     import hashlib
     try:
-        text = open(COUNTERS).read()
+        path, sources = COUNTERS[ways]
+        text = open(path).read()
         h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read()
-                                    for p in KERNEL_SOURCES)).hexdigest()[:16]
+                                    for p in sources)).hexdigest()[:16]
         fields = dict(line.split(":", 1) for line in text.splitlines()
                       if line.startswith(("merge_pass_traffic_bytes:", "kernel_source_sha256_16:")))
         if fields["kernel_source_sha256_16"].split()[0] != h:
@@ -468,6 +476,75 @@ def table2_bench():
     return res
 
 
+def measure(opts, xs, dists, out, steps, warmup):
+    """Times `steps` sorts of every input with HIP events (warm-up first),
+    plus the library's own events around the block stage and every merge
+    launch.  Returns rates and per-kernel times."""
+    n = xs[0].numel()
+    dev = xs[0].device
+    ws_bytes = hv.lib().hvms_sort_workspace_bytes(n, 0, hv._opts(opts))
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    R = opts.get("keys_per_lane") or 16
+    NT = opts.get("block_threads") or 512
+    ways = opts.get("merge_ways") or 2
+    passes = merge_passes(n, R * NT, ways)
+    levels = merge_passes(n, R * NT, 2)
+    first_dominant = levels - 2 * (levels // 2) if ways == 4 else 0  # two-way launches first
+    ev_sets = [[make_events(2 + 2 * passes) for _ in dists] for _ in range(steps)]
+
+    def step(events=None):
+        for i, x in enumerate(xs):
+            o = dict(opts)
+            if events is not None:
+                o["events"] = events[i]
+            hv.hvms_sort_i32(x, out, ws, opts=o)
+
+    log("warmup")
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    # parity spot check of the last output (cheap properties)
+    if warmup > 0:
+        last = out[: min(n, 1 << 22)]
+        assert bool((last[1:] >= last[:-1]).all()), "output not sorted"
+
+    log("timed")
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for st in range(steps):
+        step(ev_sets[st])
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t0.elapsed_time(t1)
+
+    bs_ms, pass_ms = [], [[] for _ in range(passes)]
+    per_dist = {}
+    for i, d in enumerate(dists):
+        t = []
+        for st in range(steps):
+            ev = ev_sets[st][i]
+            bs_ms.append(ev[0].elapsed_time(ev[1]))
+            for p in range(passes):
+                pass_ms[p].append(ev[2 + 2 * p].elapsed_time(ev[3 + 2 * p]))
+            t.append(ev[0].elapsed_time(ev[-1]) if passes else ev[0].elapsed_time(ev[1]))
+        per_dist[d] = round(n / (np.mean(t) / 1e3) / 1e9, 3)
+    dom = [t for p in pass_ms[first_dominant:] for t in p]
+    merge_ms = float(np.mean(dom)) if dom else float("nan")
+    pass_bytes = 8.0 * n                      # read + write every key once
+    return {
+        "R": R, "NT": NT, "passes": passes, "ws": ws,
+        "keys_per_s": steps * len(dists) * n / (ms_total / 1e3),
+        "ms_step": ms_total / steps, "wall": wall, "merge_ms": merge_ms,
+        "achieved": pass_bytes / (merge_ms / 1e3) / 1e9 if dom else 0.0,
+        "per_pass_gbs": [round(pass_bytes / (np.mean(p) / 1e3) / 1e9, 1) for p in pass_ms],
+        "bs_ms": bs_ms, "per_dist": per_dist,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -502,71 +579,17 @@ def main():
         from paper_2409_03970_amd import tune
         opts = tune.tuned_options("sort", n) or opts
     opts = {k: int(v) for k, v in opts.items()}
-    o_probe = hv._opts(opts)
-    ws_bytes = hv.lib().hvms_sort_workspace_bytes(n, 0, o_probe)
-    R = opts.get("keys_per_lane") or 16
-    NT = opts.get("block_threads") or 512
-    tile = R * NT
-    passes = merge_passes(n, tile, opts.get("merge_ways") or 2)
-
     log(f"generating {len(dists)} x 2^{log2n} keys")
     xs = [inputs.keys(n, d, seed=0, device=dev) for d in dists]
     out = torch.empty(n, dtype=torch.int32, device=dev)
-    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
-    n_ev = 2 + 2 * passes
-    ev_sets = [[make_events(n_ev) for _ in dists] for _ in range(args.steps)]
-
-    def step(events=None):
-        for i, x in enumerate(xs):
-            o = dict(opts)
-            if events is not None:
-                o["events"] = events[i]
-            hv.hvms_sort_i32(x, out, ws, opts=o)
-
-    log("warmup")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    # parity spot check of the last output against the input (cheap properties)
-    if args.warmup > 0:
-        last = out[: min(n, 1 << 22)]
-        assert bool((last[1:] >= last[:-1]).all()), "output not sorted"
-
-    log("timed")
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    t0.record()
-    for s in range(args.steps):
-        step(ev_sets[s])
-    t1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_total = t0.elapsed_time(t1)
-    ms_step = ms_total / args.steps
-    keys_per_s = args.steps * len(dists) * n / (ms_total / 1e3)
-
-    # per-kernel times from the library's trace events
-    bs_ms, pass_ms = [], [[] for _ in range(passes)]
-    for s in range(args.steps):
-        for i in range(len(dists)):
-            ev = ev_sets[s][i]
-            bs_ms.append(ev[0].elapsed_time(ev[1]))
-            for p in range(passes):
-                pass_ms[p].append(ev[2 + 2 * p].elapsed_time(ev[3 + 2 * p]))
-    merge_ms = float(np.mean([t for p in pass_ms for t in p])) if passes else float("nan")
-    pass_bytes = 8.0 * n                      # read + write every key once
-    achieved = pass_bytes / (merge_ms / 1e3) / 1e9 if passes else 0.0
-    per_pass_gbs = [round(pass_bytes / (np.mean(p) / 1e3) / 1e9, 1) for p in pass_ms]
-
-    per_dist = {}
-    for i, d in enumerate(dists):
-        t = []
-        for s in range(args.steps):
-            ev = ev_sets[s][i]
-            t.append(ev[0].elapsed_time(ev[-1]) if passes else ev[0].elapsed_time(ev[1]))
-        per_dist[d] = round(n / (np.mean(t) / 1e3) / 1e9, 3)
+    M = measure(opts, xs, dists, out, args.steps, args.warmup)
+    R, NT, tile, passes = M["R"], M["NT"], M["R"] * M["NT"], M["passes"]
+    keys_per_s, ms_step, wall = M["keys_per_s"], M["ms_step"], M["wall"]
+    merge_ms, achieved, per_pass_gbs = M["merge_ms"], M["achieved"], M["per_pass_gbs"]
+    bs_ms, per_dist = M["bs_ms"], M["per_dist"]
+    pass_bytes = 8.0 * n
+    ways = opts.get("merge_ways") or 2
+    ws = M["ws"]
 
     rec = {
         "metric": METRIC,
@@ -591,11 +614,13 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": {
-            "kernel": "merge_pass_kernel (global merge pass)",
+            "kernel": ("merge4_pipe_kernel (four-way merge pass: two merge levels per launch)"
+                       if ways == 4 else "merge_pass_pipe_kernel (two-way merge pass)"),
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": counter_traffic() if log2n == 28 else None,
+            "traffic": counter_traffic(ways) if log2n == 28 else None,
             "bytes_per_launch": pass_bytes, "avg_launch_ms": merge_ms,
+            "merge_levels_per_launch": 2 if ways == 4 else 1,
         },
         "merge_pass_gbs": per_pass_gbs,
         "block_sort_ms": float(np.mean(bs_ms)) if bs_ms else None,
@@ -608,7 +633,19 @@ def main():
     if not args.quick:
         log("corank_modes_2p28")
         try:
-            rec["corank_modes_2p28"] = corank_modes(xs, dists, out, ws, opts)
+            # the co-rank the model predicts is the two-way pass's: compare
+            # the modes on the best two-way configuration
+            oc = opts
+            if ways == 4:
+                from paper_2409_03970_amd import tune
+                oc = tune.tuned_options("sort", n, two_way=True) or {
+                    "keys_per_lane": 32, "block_threads": 512, "wave_levels": 7,
+                    "merge_tile": 8192}
+                oc = {k: int(v) for k, v in oc.items()}
+            wsc = torch.empty(max(hv.lib().hvms_sort_workspace_bytes(n, 0, hv._opts(oc)), 1),
+                              dtype=torch.uint8, device=dev)
+            rec["corank_modes_2p28"] = dict(corank_modes(xs, dists, out, wsc, oc), options=oc)
+            del wsc
         except Exception as e:  # an extra must never cost the headline line
             rec["corank_modes_2p28"] = {"error": repr(e)}
         log("key_types_2p28")
@@ -616,13 +653,36 @@ def main():
             rec["key_types_2p28"] = key_types_bench(n)
         except Exception as e:
             rec["key_types_2p28"] = {"error": repr(e)}
-        log("four_way_2p28")
-        try:
-            hv.hvms_sort_i32(xs[0], out, ws, opts=opts)
-            rec["four_way_2p28_" + dists[0]] = four_way_bench(xs[0], out, opts)
-        except Exception as e:
-            rec["four_way_2p28_" + dists[0]] = {"error": repr(e)}
-        del xs, out, ws, ev_sets
+        if ways == 4:
+            # the best configuration with two-way passes on the same inputs:
+            # one merge level per trip through HBM, at a higher share of the
+            # bandwidth per launch
+            log("two_way_2p28")
+            try:
+                from paper_2409_03970_amd import tune
+                o2 = tune.tuned_options("sort", n, two_way=True) or {
+                    "keys_per_lane": 32, "block_threads": 512, "wave_levels": 7,
+                    "merge_tile": 8192}
+                o2 = {k: int(v) for k, v in o2.items()}
+                M2 = measure(o2, xs, dists, out, args.steps, 1)
+                rec["two_way_2p28"] = {
+                    "value": M2["keys_per_s"], "options": o2,
+                    "gkeys_per_s_by_distribution": M2["per_dist"],
+                    "merge_pass_gbs": M2["per_pass_gbs"], "avg_launch_ms": M2["merge_ms"],
+                    "frac": round(M2["achieved"] / HBM_PEAK_GBS, 4),
+                    "traffic": counter_traffic(2),
+                    "block_sort_ms": float(np.mean(M2["bs_ms"]))}
+                del M2
+            except Exception as e:
+                rec["two_way_2p28"] = {"error": repr(e)}
+        else:
+            log("four_way_2p28")
+            try:
+                hv.hvms_sort_i32(xs[0], out, ws, opts=opts)
+                rec["four_way_2p28_" + dists[0]] = four_way_bench(xs[0], out, opts)
+            except Exception as e:
+                rec["four_way_2p28_" + dists[0]] = {"error": repr(e)}
+        del xs, out, ws, M
         torch.cuda.empty_cache()
         extras = (("in_register_sort_table2", table2_bench),
                   ("merge_table3", lambda: merge_table3_bench(n)),

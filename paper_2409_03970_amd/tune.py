@@ -41,8 +41,9 @@ def load_cache(path=CACHE):
         return json.load(f)
 
 
-def tuned_options(op, n, path=CACHE):
-    """Cached options for (op, nearest size bucket) on this device, or None."""
+def tuned_options(op, n, path=CACHE, two_way=False):
+    """Cached options for (op, nearest size bucket) on this device, or None
+    (two_way: the best configuration restricted to two-way passes)."""
     if not torch.cuda.is_available() or n <= 0:
         return None
     cache = load_cache(path)
@@ -55,8 +56,9 @@ def tuned_options(op, n, path=CACHE):
         if len(parts) != 4 or ":".join(parts[:3]) != _key(op, 0).rsplit(":", 1)[0]:
             continue
         d = abs(int(parts[3]) - log2n)
-        if d <= 2 and (best is None or d < best[0]):
-            best = (d, v["options"])
+        o = v.get("two_way", {}).get("options") if two_way else v["options"]
+        if o is not None and d <= 2 and (best is None or d < best[0]):
+            best = (d, o)
     return dict(best[1]) if best else None
 
 
@@ -147,8 +149,13 @@ def tune(op="sort", log2n=24, nseg=200000, seg_max=65536, reps=5, seed=0, path=C
     results.sort(key=lambda r: r[0])
     best_ms, best = results[0]
     cache = load_cache(path)
-    cache[_key(op, log2n)] = {"options": best, "ms": best_ms, "default_ms": base_ms, "n": n,
-                              "candidates": len(results)}
+    entry = {"options": best, "ms": best_ms, "default_ms": base_ms, "n": n,
+             "candidates": len(results)}
+    # the best configuration with two-way passes only, for comparison
+    two = next((r for r in results if r[1].get("merge_ways", 2) == 2), None)
+    if two is not None:
+        entry["two_way"] = {"options": two[1], "ms": two[0]}
+    cache[_key(op, log2n)] = entry
     with open(path, "w") as fh:
         json.dump(cache, fh, indent=1, sort_keys=True)
     if verbose:
