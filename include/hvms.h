@@ -168,6 +168,36 @@ int hvms_sort_pairs_f32(const float *d_keys_in, const int32_t *d_vals_in,
                         const hvms_options *opt);
 
 /*
+ * 64-bit keys (the 64-bit key types of the same sort).  Each key is handled
+ * as one 64-bit element: the key-value machinery of hvms_sort_pairs_i32 orders
+ * (high word, low word) lexicographically, and a 64-bit key in that form
+ * (low word with its sign bit flipped) compares exactly as the signed 64-bit
+ * integer, so the same kernels sort it.  The block stage reads the packed
+ * array and the last launch writes it; the passes in between use split
+ * buffers in the workspace.
+ *   hvms_sort_i64:  signed order.
+ *   hvms_sort_u64:  unsigned order.
+ *   hvms_sort_f64:  IEEE 754 totalOrder of the bit patterns (as
+ *                   hvms_sort_f32, for binary64); every bit pattern is
+ *                   preserved.
+ *   d_in, d_out     device arrays of n 64-bit elements, 8-byte aligned (else
+ *                   HVMS_ERR_INVALID_ARG); they may be equal.  An output that
+ *                   is 16-byte aligned takes the fastest path.
+ *   d_ws/ws_bytes   workspace, >= hvms_sort64_workspace_bytes(n, opt) (16 bytes
+ *                   per key plus co-ranks once n exceeds one block tile),
+ *                   256-byte aligned.
+ * Tuning values are those of hvms_sort_pairs_i32 (merge_variant 4 is not
+ * available).  n == 0 is a no-op.
+ */
+int64_t hvms_sort64_workspace_bytes(int64_t n, const hvms_options *opt);
+int hvms_sort_i64(const int64_t *d_in, int64_t *d_out, int64_t n, void *d_ws,
+                  size_t ws_bytes, void *stream, const hvms_options *opt);
+int hvms_sort_u64(const uint64_t *d_in, uint64_t *d_out, int64_t n, void *d_ws,
+                  size_t ws_bytes, void *stream, const hvms_options *opt);
+int hvms_sort_f64(const double *d_in, double *d_out, int64_t n, void *d_ws,
+                  size_t ws_bytes, void *stream, const hvms_options *opt);
+
+/*
  * Sort every run of 2^run_log2 consecutive keys independently (the last run
  * may be shorter): the block stage alone, i.e. "every X elements in order"
  * of Table 2 with X = 2^run_log2.  run_log2 must lie in

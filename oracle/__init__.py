@@ -40,6 +40,9 @@ def lib():
         _u32p = ctypes.POINTER(ctypes.c_uint32)
         for name in ("oracle_sort_u32", "oracle_sort_f32"):
             getattr(L, name).argtypes = [_u32p, ctypes.c_int64]
+        _u64p = ctypes.POINTER(ctypes.c_uint64)
+        for name in ("oracle_sort_i64", "oracle_sort_u64", "oracle_sort_f64"):
+            getattr(L, name).argtypes = [_u64p, ctypes.c_int64]
         for name in ("oracle_sort_pairs_u32", "oracle_sort_pairs_f32"):
             getattr(L, name).argtypes = [_u32p, _i32p, ctypes.c_int64]
         L.oracle_segmented_sort_i32.argtypes = [_i32p, _i64p, ctypes.c_int64]
@@ -115,6 +118,29 @@ def sort_f32(keys):
     if lib().oracle_sort_f32(a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), a.size) != 0:
         raise MemoryError("oracle sort failed")
     return a.view(np.float32)
+
+
+def _sort64(fn, keys, dtype):
+    a = np.ascontiguousarray(np.array(keys, dtype=dtype, copy=True).view(np.uint64))
+    if fn(a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), a.size) != 0:
+        raise MemoryError("oracle sort failed")
+    return a.view(dtype)
+
+
+def sort_i64(keys):
+    """Sorted copy of int64 keys (signed order)."""
+    return _sort64(lib().oracle_sort_i64, keys, np.int64)
+
+
+def sort_u64(keys):
+    """Sorted copy of uint64 keys (unsigned order)."""
+    return _sort64(lib().oracle_sort_u64, keys, np.uint64)
+
+
+def sort_f64(keys):
+    """Sorted copy of float64 keys in IEEE 754 totalOrder (bit-exact: -0
+    before +0, NaNs placed by sign and payload)."""
+    return _sort64(lib().oracle_sort_f64, keys, np.float64)
 
 
 def _sort_pairs_gen(fn, a, vals):

@@ -16,6 +16,9 @@
  *                     signed 32-bit order;
  *   - sort of pairs:  the nondecreasing arrangement in lexicographic
  *                     (key, value) order, both signed;
+ *   - other key types: the same with the type's own order (uint32/uint64
+ *                     unsigned, float32/float64 IEEE 754 totalOrder,
+ *                     int64 signed);
  *   - segmented:      the above applied to each segment independently;
  *   - co-rank:        the number of elements of A among the first d outputs
  *                     of the merge of sorted A and B that takes A first on
@@ -222,6 +225,72 @@ int oracle_sort_pairs_f32(uint32_t *bits, int32_t *v, int64_t n)
 {
     return sort_gen(less_f32_total, bits, v, n);
 }
+
+/* ------------------------------------------------------------ 64-bit keys */
+
+/*
+ * 64-bit keys, with the order written out for each type:
+ *   - int64: signed order;
+ *   - uint64: unsigned order;
+ *   - float64: IEEE 754-2008 totalOrder (5.10) on the binary64 bit patterns,
+ *     by the same rule as float32 above: sign bit set first; magnitudes (the
+ *     63 bits below the sign, read as one unsigned integer) ascending among
+ *     positives and descending among negatives.
+ * Same stable top-down merge sort, on 64-bit words.
+ */
+typedef int (*less64_fn)(uint64_t, uint64_t);
+
+static int less_i64(uint64_t a, uint64_t b) { return (int64_t)a < (int64_t)b; }
+
+static int less_u64(uint64_t a, uint64_t b) { return a < b; }
+
+static int less_f64_total(uint64_t a, uint64_t b)
+{
+    uint64_t sa = a >> 63, sb = b >> 63;
+    if (sa != sb)
+        return sa > sb;
+    uint64_t ma = a & 0x7fffffffffffffffull, mb = b & 0x7fffffffffffffffull;
+    return sa ? ma > mb : ma < mb;
+}
+
+static void msort64(less64_fn less, uint64_t *k, uint64_t *aux, int64_t lo, int64_t hi)
+{
+    if (hi - lo < 2)
+        return;
+    int64_t mid = lo + (hi - lo) / 2;
+    msort64(less, k, aux, lo, mid);
+    msort64(less, k, aux, mid, hi);
+    int64_t i = lo, j = mid, o = lo;
+    while (i < mid || j < hi) {
+        int take_j;
+        if (i == mid)
+            take_j = 1;
+        else if (j == hi)
+            take_j = 0;
+        else
+            take_j = less(k[j], k[i]);
+        aux[o++] = take_j ? k[j++] : k[i++];
+    }
+    memcpy(k + lo, aux + lo, (size_t)(hi - lo) * sizeof(uint64_t));
+}
+
+static int sort64(less64_fn less, uint64_t *k, int64_t n)
+{
+    if (n < 0)
+        return -1;
+    if (n < 2)
+        return 0;
+    uint64_t *aux = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    if (!aux)
+        return -1;
+    msort64(less, k, aux, 0, n);
+    free(aux);
+    return 0;
+}
+
+int oracle_sort_i64(uint64_t *k, int64_t n) { return sort64(less_i64, k, n); }
+int oracle_sort_u64(uint64_t *k, int64_t n) { return sort64(less_u64, k, n); }
+int oracle_sort_f64(uint64_t *bits, int64_t n) { return sort64(less_f64_total, bits, n); }
 
 /* ------------------------------------------------------------- segmented */
 

@@ -22,7 +22,8 @@ __all__ = [
     "segmented_sort_pairs", "cdf_forward", "cdf_backward", "cdf_adam_step", "cdf_train",
     "hvms_cdf_sample_i32", "cdf_sample", "fit_cdf_model", "segmented_sort_pairs_grouped",
     "segment_groups", "hvms_sort_u32", "hvms_sort_f32", "hvms_sort_pairs_u32",
-    "hvms_sort_pairs_f32", "sort_keys", "sort_pairs_keys",
+    "hvms_sort_pairs_f32", "sort_keys", "sort_pairs_keys", "hvms_sort_i64", "hvms_sort_u64",
+    "hvms_sort_f64",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -80,6 +81,10 @@ _SIGS = {
     "hvms_sort_f32": ([_vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
     "hvms_sort_pairs_u32": ([_vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
     "hvms_sort_pairs_f32": ([_vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
+    "hvms_sort64_workspace_bytes": ([_i64, _opt], _i64),
+    "hvms_sort_i64": ([_vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
+    "hvms_sort_u64": ([_vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
+    "hvms_sort_f64": ([_vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
     "hvms_merge_workspace_bytes": ([_i64, _i64, _opt], _i64),
     "hvms_merge_pass_i32": ([_vp, _vp, _i64, _i64, _vp, _sz, _vp, _opt], _i32),
     "hvms_corank_i32": ([_vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _opt], _i32),
@@ -191,8 +196,10 @@ def hvms_sort_pairs_i32(k_in, v_in, k_out, v_out, ws=None, stream=None, opts=Non
         _ptr(v_out, torch.int32), k_in.numel(), p, b, _stream(stream), _opts(opts)))
 
 
-# uint32 keys may come as torch.uint32 or as int32 bit patterns
-_KEY_DTYPES = {"u32": (torch.uint32, torch.int32), "f32": (torch.float32,)}
+# unsigned keys may come as torch.uint32 / uint64 or as signed bit patterns
+_KEY_DTYPES = {"u32": (torch.uint32, torch.int32), "f32": (torch.float32,),
+               "i64": (torch.int64,), "u64": (torch.uint64, torch.int64),
+               "f64": (torch.float64,)}
 
 
 def _kptr(t, kind, name):
@@ -213,6 +220,26 @@ def hvms_sort_f32(d_in, d_out, ws=None, stream=None, opts=None):
     _check("hvms_sort_f32", lib().hvms_sort_f32(
         _kptr(d_in, "f32", "in"), _kptr(d_out, "f32", "out"), d_in.numel(), p, b,
         _stream(stream), _opts(opts)))
+
+
+def _sort64(fn, kind, d_in, d_out, ws, stream, opts):
+    assert d_in.numel() == d_out.numel()
+    p, b = _wsargs(ws)
+    _check(fn, getattr(lib(), fn)(
+        _kptr(d_in, kind, "in"), _kptr(d_out, kind, "out"), d_in.numel(), p, b,
+        _stream(stream), _opts(opts)))
+
+
+def hvms_sort_i64(d_in, d_out, ws=None, stream=None, opts=None):
+    _sort64("hvms_sort_i64", "i64", d_in, d_out, ws, stream, opts)
+
+
+def hvms_sort_u64(d_in, d_out, ws=None, stream=None, opts=None):
+    _sort64("hvms_sort_u64", "u64", d_in, d_out, ws, stream, opts)
+
+
+def hvms_sort_f64(d_in, d_out, ws=None, stream=None, opts=None):
+    _sort64("hvms_sort_f64", "f64", d_in, d_out, ws, stream, opts)
 
 
 def _sort_pairs_mapped(fn, kind, k_in, v_in, k_out, v_out, ws, stream, opts):
@@ -331,11 +358,25 @@ def sort_pairs(keys, vals, keys_out=None, vals_out=None, opts=None, stream=None)
     return keys_out, vals_out
 
 
+_SORT64 = {torch.int64: hvms_sort_i64, torch.uint64: hvms_sort_u64,
+           torch.float64: hvms_sort_f64}
+
+
 def sort_keys(keys, out=None, opts=None, stream=None):
-    """Sorted copy of a device tensor of int32, uint32 (torch.uint32) or
-    float32 keys (IEEE 754 totalOrder); out may be keys (in place)."""
+    """Sorted copy of a device tensor of int32, uint32 (torch.uint32), float32
+    (IEEE 754 totalOrder), int64, uint64 (torch.uint64) or float64 keys; out
+    may be keys (in place)."""
     if keys.dtype == torch.int32:
         return sort(keys, out, opts, stream)
+    fn64 = _SORT64.get(keys.dtype)
+    if fn64 is not None:
+        # 64-bit keys run on the key-value kernels: their tuning applies
+        opts = _auto("sort_pairs", keys.numel(), opts)
+        out = torch.empty_like(keys) if out is None else out
+        ws = _workspace(lib().hvms_sort64_workspace_bytes(keys.numel(), _opts(opts)),
+                        keys.device)
+        fn64(keys, out, ws, stream, opts)
+        return out
     fn = {torch.uint32: hvms_sort_u32, torch.float32: hvms_sort_f32}.get(keys.dtype)
     if fn is None:
         raise ValueError(f"unsupported key dtype {keys.dtype}")

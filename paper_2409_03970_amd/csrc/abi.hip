@@ -91,10 +91,13 @@ int resolve(const hvms_options *o, bool pairs, Cfg &c)
 }
 
 struct SortWs {
-    int64_t scratch_k, scratch_v, coranks, records, total;
+    int64_t scratch_k, scratch_v, alt_k, alt_v, coranks, records, total;
 };
 
-SortWs sort_ws_layout(int64_t n, bool pairs, const Cfg &c)
+// packed: a 64-bit key sort, whose passes ping-pong between two split
+// (key, value) buffer pairs in the workspace, since the caller's arrays hold
+// the packed form.
+SortWs sort_ws_layout(int64_t n, bool pairs, const Cfg &c, bool packed = false)
 {
     SortWs w{};
     const int64_t tile = (int64_t)c.R * c.NT;
@@ -104,6 +107,12 @@ SortWs sort_ws_layout(int64_t n, bool pairs, const Cfg &c)
     int64_t off = align256(n * 4);
     if (pairs) {
         w.scratch_v = off;
+        off += align256(n * 4);
+    }
+    if (packed) {
+        w.alt_k = off;
+        off += align256(n * 4);
+        w.alt_v = off;
         off += align256(n * 4);
     }
     const int64_t ntiles = (n + c.TM - 1) / c.TM;
@@ -126,8 +135,9 @@ int check_ws(void *ws, size_t bytes, int64_t need)
     return HVMS_OK;
 }
 
-// km: the key map of a uint32 or float32 sort, applied as the keys are
-// loaded by the block stage and undone as the last launch stores them.
+// km: the key map of a uint32 / float32 / 64-bit sort, applied as the keys
+// are loaded by the block stage and undone as the last launch stores them;
+// km.packed: kin and kout are packed 64-bit key arrays (pairs must be set).
 int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
              int64_t n, void *ws, hipStream_t s, const Cfg &c, KeyMap km = {})
 {
@@ -140,19 +150,28 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
             launch_block_sort(c.R, c.NT, pairs, kin, vin, kout, vout, n, K, lds_levels, false, s,
                               c.net, km, km));
 
-    const SortWs w = sort_ws_layout(n, pairs, c);
+    const SortWs w = sort_ws_layout(n, pairs, c, km.packed);
     char *base = (char *)ws;
     int32_t *sk = (int32_t *)(base + w.scratch_k);
     int32_t *sv = pairs ? (int32_t *)(base + w.scratch_v) : nullptr;
     int64_t *cr = (int64_t *)(base + w.coranks);
+    // the passes alternate between (ak, av) and (sk, sv); the last one
+    // writes the caller's arrays, in packed form for a 64-bit key sort
+    int32_t *ak = km.packed ? (int32_t *)(base + w.alt_k) : kout;
+    int32_t *av = km.packed ? (int32_t *)(base + w.alt_v) : vout;
 
+    // Four-way passes move 16-byte chunks of the arrays they read and write:
+    // a caller's output that is not 16-byte aligned takes two-way passes,
+    // whose launcher has a fallback for it.
+    const bool out_aligned =
+        (uintptr_t)kout % 16 == 0 && (!pairs || km.packed || (uintptr_t)vout % 16 == 0);
     const int64_t nb = (n + tile - 1) / tile;
-    const int P = ilog2_exact(nb);           // merge levels
-    const int P4 = c.ways == 4 ? P / 2 : 0;  // four-way passes (two levels each)
-    const int P2 = P - 2 * P4;               // two-way passes (first)
+    const int P = ilog2_exact(nb);  // merge levels
+    const int P4 = c.ways == 4 && out_aligned ? P / 2 : 0;  // four-way passes (two levels each)
+    const int P2 = P - 2 * P4;                               // two-way passes (first)
     const int passes = P2 + P4;
-    int32_t *dk = (passes % 2 == 0) ? kout : sk;
-    int32_t *dv = (passes % 2 == 0) ? vout : sv;
+    int32_t *dk = (passes % 2 == 0) ? ak : sk;
+    int32_t *dv = (passes % 2 == 0) ? av : sv;
     trace(c, 0, s);
     int st = hip_status(
         launch_block_sort(c.R, c.NT, pairs, kin, vin, dk, dv, n, K, lds_levels, false, s,
@@ -162,8 +181,12 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
     trace(c, 1, s);
     int64_t run = tile;
     for (int p = 0; p < passes; ++p) {
-        int32_t *ok = (dk == kout) ? sk : kout;
-        int32_t *ov = (dk == kout) ? sv : vout;
+        int32_t *ok = (dk == ak) ? sk : ak;
+        int32_t *ov = (dk == ak) ? sv : av;
+        if (p == passes - 1) {
+            ok = kout;
+            ov = km.packed ? nullptr : vout;
+        }
         if (p >= P2) {
             st = hip_status(launch_merge4_corank(c.TM, pairs, dk, dv, n, run, cr,
                                                  base + w.records, c.co, s));
@@ -313,9 +336,71 @@ int sort_pairs_mapped(const void *d_keys_in, const int32_t *d_vals_in, void *d_k
                     d_vals_out, n, d_ws, (hipStream_t)stream, c, key_map_of(kind));
 }
 
+KeyMap key_map64_of(int kind)  // 0 int64, 1 uint64, 2 float64
+{
+    KeyMap m;
+    m.packed = true;
+    if (kind == 1) {
+        m.um = (int32_t)0x80000000u;
+    } else if (kind == 2) {
+        m.fm = 0x7fffffff;
+        m.fl = -1;
+    }
+    return m;
+}
+
+int sort_keys64(const void *d_in, void *d_out, int64_t n, void *d_ws, size_t ws_bytes,
+                void *stream, const hvms_options *opt, int kind)
+{
+    if (n < 0 || (n > 0 && (!d_in || !d_out)))
+        return HVMS_ERR_INVALID_ARG;
+    if (n > 0 && (((uintptr_t)d_in | (uintptr_t)d_out) & 7))  // 64-bit elements
+        return HVMS_ERR_INVALID_ARG;
+    Cfg c;
+    int st = resolve(opt, true, c);
+    if (st)
+        return st;
+    if (n == 0)
+        return HVMS_OK;
+    st = check_ws(d_ws, ws_bytes, sort_ws_layout(n, true, c, true).total);
+    if (st)
+        return st;
+    return run_sort(true, (const int32_t *)d_in, nullptr, (int32_t *)d_out, nullptr, n, d_ws,
+                    (hipStream_t)stream, c, key_map64_of(kind));
+}
+
 }  // namespace
 
 extern "C" {
+
+int64_t hvms_sort64_workspace_bytes(int64_t n, const hvms_options *opt)
+{
+    Cfg c;
+    if (n < 0)
+        return HVMS_ERR_INVALID_ARG;
+    const int st = resolve(opt, true, c);
+    if (st)
+        return st;
+    return sort_ws_layout(n, true, c, true).total;
+}
+
+int hvms_sort_i64(const int64_t *d_in, int64_t *d_out, int64_t n, void *d_ws, size_t ws_bytes,
+                  void *stream, const hvms_options *opt)
+{
+    return sort_keys64(d_in, d_out, n, d_ws, ws_bytes, stream, opt, 0);
+}
+
+int hvms_sort_u64(const uint64_t *d_in, uint64_t *d_out, int64_t n, void *d_ws, size_t ws_bytes,
+                  void *stream, const hvms_options *opt)
+{
+    return sort_keys64(d_in, d_out, n, d_ws, ws_bytes, stream, opt, 1);
+}
+
+int hvms_sort_f64(const double *d_in, double *d_out, int64_t n, void *d_ws, size_t ws_bytes,
+                  void *stream, const hvms_options *opt)
+{
+    return sort_keys64(d_in, d_out, n, d_ws, ws_bytes, stream, opt, 2);
+}
 
 int hvms_sort_u32(const uint32_t *d_in, uint32_t *d_out, int64_t n, void *d_ws, size_t ws_bytes,
                   void *stream, const hvms_options *opt)

@@ -12,13 +12,14 @@
 //       levels merge them further, each thread producing R outputs by a
 //       serial merge from its co-rank;
 // then the tile is written back with coalesced stores.  Ragged tiles are
-// padded with the maximum of the order.
+// padded with the maximum of the order.  PKM (64-bit elements only): bit 0,
+// the input is one packed 64-bit array at kin; bit 1, so is the output.
 #include "common.h"
 #include "hvms_internal.h"
 
 namespace hvms {
 
-template <int R, int NT, typename T, int NET = 0>
+template <int R, int NT, typename T, int NET = 0, int PKM = 0>
 __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restrict__ kin,
                                                         const int32_t *__restrict__ vin,
                                                         int32_t *__restrict__ kout,
@@ -27,6 +28,7 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
                                                         bool blocked, KeyMap xin, KeyMap xout)
 {
     constexpr int TILE = R * NT;
+    constexpr bool PI = (PKM & 1) != 0, PO = (PKM & 2) != 0;
     __shared__ __attribute__((aligned(16))) T S[LdsSkew<T>::size(TILE)];
     const LdsSkew<T> Z{S, 0};
     const int t = threadIdx.x;
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int64_t g = tile0 + t + NT * j;
-            Z[t + NT * j] = g < n ? map_elem(load_elem<T>(kin, vin, g), xin) : Traits<T>::kMax;
+            Z[t + NT * j] = g < n ? map_elem(load_elem<T, PI>(kin, vin, g), xin) : Traits<T>::kMax;
         }
         __syncthreads();
         const LdsSkew<T> W{S, wave * (64 * R) + lane * R};
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
     } else if (tile0 + TILE <= n) {
 #pragma unroll
         for (int j = 0; j < R; ++j)
-            v[j] = load_elem<T>(kin, vin, wave0 + 64 * j + lane);
+            v[j] = load_elem<T, PI>(kin, vin, wave0 + 64 * j + lane);
         if (key_map_on(xin)) {  // wave-uniform
 #pragma unroll
             for (int j = 0; j < R; ++j)
@@ -64,7 +66,7 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int64_t g = wave0 + 64 * j + lane;
-            v[j] = g < n ? map_elem(load_elem<T>(kin, vin, g), xin) : Traits<T>::kMax;
+            v[j] = g < n ? map_elem(load_elem<T, PI>(kin, vin, g), xin) : Traits<T>::kMax;
         }
     }
 
@@ -73,30 +75,54 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
     if (tile0 + TILE <= n && !key_map_on(xout)) {
 #pragma unroll
         for (int j = 0; j < R; ++j)
-            store_elem<T>(kout, vout, tile0 + t + NT * j, Z[t + NT * j]);
+            store_elem<T, PO>(kout, vout, tile0 + t + NT * j, Z[t + NT * j]);
     } else if (tile0 + TILE <= n) {
 #pragma unroll
         for (int j = 0; j < R; ++j)
-            store_elem<T>(kout, vout, tile0 + t + NT * j, map_elem(Z[t + NT * j], xout));
+            store_elem<T, PO>(kout, vout, tile0 + t + NT * j, map_elem(Z[t + NT * j], xout));
     } else {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int64_t g = tile0 + t + NT * j;
             if (g < n)
-                store_elem<T>(kout, vout, g, map_elem(Z[t + NT * j], xout));
+                store_elem<T, PO>(kout, vout, g, map_elem(Z[t + NT * j], xout));
         }
     }
 }
 
+template <int R, int NT, typename T, int NET = 0, int PKM = 0>
+static hipError_t launch_bs1(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
+                             int64_t n, int wave_levels, int lds_levels, bool blocked,
+                             hipStream_t s, KeyMap xin, KeyMap xout)
+{
+    const int64_t tiles = (n + R * NT - 1) / (R * NT);
+    hipLaunchKernelGGL((block_sort_kernel<R, NT, T, NET, PKM>), dim3((unsigned)tiles), dim3(NT), 0,
+                       s, kin, vin, kout, vout, n, wave_levels, lds_levels, blocked, xin, xout);
+    return hipGetLastError();
+}
+
+// Packed 64-bit arrays: a packed input with split output (the block stage
+// of a longer sort) or packed on both sides (a sort of one tile).
 template <int R, int NT, typename T, int NET = 0>
 static hipError_t launch_bs(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
                             int64_t n, int wave_levels, int lds_levels, bool blocked,
                             hipStream_t s, KeyMap xin, KeyMap xout)
 {
-    const int64_t tiles = (n + R * NT - 1) / (R * NT);
-    hipLaunchKernelGGL((block_sort_kernel<R, NT, T, NET>), dim3((unsigned)tiles), dim3(NT), 0, s, kin,
-                       vin, kout, vout, n, wave_levels, lds_levels, blocked, xin, xout);
-    return hipGetLastError();
+    if constexpr (sizeof(T) == 8) {
+        if (xin.packed || xout.packed) {
+            if (!xin.packed)
+                return hipErrorInvalidValue;
+            return xout.packed
+                       ? launch_bs1<R, NT, T, NET, 3>(kin, vin, kout, vout, n, wave_levels,
+                                                      lds_levels, blocked, s, xin, xout)
+                       : launch_bs1<R, NT, T, NET, 1>(kin, vin, kout, vout, n, wave_levels,
+                                                      lds_levels, blocked, s, xin, xout);
+        }
+    } else if (xin.packed || xout.packed) {
+        return hipErrorInvalidValue;
+    }
+    return launch_bs1<R, NT, T, NET>(kin, vin, kout, vout, n, wave_levels, lds_levels, blocked, s,
+                                     xin, xout);
 }
 
 bool block_sort_supported(int R, int NT, bool pairs)

@@ -34,22 +34,27 @@ __device__ __forceinline__ int32_t pair_val(int64_t p)
     return (int32_t)((uint32_t)(uint64_t)p ^ 0x80000000u);
 }
 
-// Element i of a key array, or of a key/value array pair, as type T.
-template <typename T>
+// Element i of a key array, or of a key/value array pair, as type T.  PK:
+// the 64-bit elements sit packed at k (a 64-bit key array; v unused).
+template <typename T, bool PK = false>
 __device__ __forceinline__ T load_elem(const int32_t *__restrict__ k,
                                        const int32_t *__restrict__ v, int64_t i)
 {
     if constexpr (sizeof(T) == 4)
         return k[i];
+    else if constexpr (PK)
+        return ((const int64_t *)k)[i];
     else
         return pack_pair(k[i], v[i]);
 }
-template <typename T>
+template <typename T, bool PK = false>
 __device__ __forceinline__ void store_elem(int32_t *__restrict__ k, int32_t *__restrict__ v,
                                            int64_t i, T x)
 {
     if constexpr (sizeof(T) == 4) {
         k[i] = x;
+    } else if constexpr (PK) {
+        ((int64_t *)k)[i] = x;
     } else {
         k[i] = pair_key(x);
         v[i] = pair_val(x);
@@ -58,17 +63,20 @@ __device__ __forceinline__ void store_elem(int32_t *__restrict__ k, int32_t *__r
 
 // Key maps (see KeyMap): the element with its key mapped; pads are never
 // mapped, so the callers apply these to real elements only.
-__device__ __forceinline__ bool key_map_on(KeyMap m) { return (m.um | m.fm) != 0; }
+__device__ __forceinline__ bool key_map_on(KeyMap m) { return (m.um | m.fm | m.fl) != 0; }
 __device__ __forceinline__ int32_t key_map(int32_t b, KeyMap m)
 {
     return b ^ (((b >> 31) & m.fm) | m.um);
 }
 template <typename T> __device__ __forceinline__ T map_elem(T x, KeyMap m)
 {
-    if constexpr (sizeof(T) == 4)
+    if constexpr (sizeof(T) == 4) {
         return key_map(x, m);
-    else
-        return pack_pair(key_map(pair_key(x), m), pair_val(x));
+    } else {
+        const int64_t f = (int64_t)(((uint64_t)(uint32_t)m.fm << 32) | (uint32_t)m.fl);
+        const int64_t u = (int64_t)((uint64_t)(uint32_t)m.um << 32);
+        return x ^ (((x >> 63) & f) | u);
+    }
 }
 
 // ---------------------------------------------------------------- comparators

@@ -9,13 +9,24 @@ namespace hvms {
 // abi.hip: the hipError_t reported by hvms_last_hip_error (thread-local)
 void set_last_hip_error(int e);
 
-// Order-preserving map of another 32-bit key type onto int32 order, applied
-// to keys as they are first loaded and again (it is its own inverse) as they
-// are finally stored: key ^ (((key >> 31) & fm) | um).  uint32: um = sign bit;
-// float32: fm = 0x7fffffff (IEEE 754 totalOrder of the bit patterns);
-// int32: both 0 (identity).
+// What happens to elements at the boundary of a sort: as they are first
+// loaded (block stage) and as they are finally stored (last launch).
+//
+// Key map: an order-preserving map of another key type onto signed order,
+// its own inverse.  32-bit keys: key ^ (((key >> 31) & fm) | um); uint32:
+// um = sign bit; float32: fm = 0x7fffffff (IEEE 754 totalOrder of the bit
+// patterns); int32: both 0 (identity).  Pair elements map their key the
+// same way.  64-bit keys are pair elements (high word = key, low word =
+// value with its sign bit flipped, see common.h), and the map of the whole
+// 64-bit word is x ^ (((x >> 63) & (fm:fl)) | (um:0)): uint64 um = sign bit,
+// float64 fm = 0x7fffffff and fl = 0xffffffff.
+//
+// packed: the array on that side holds 64-bit elements at the key pointer
+// (an int64 / uint64 / float64 key array) instead of separate key and value
+// int32 arrays; the sort's intermediate buffers stay split.
 struct KeyMap {
-    int32_t um = 0, fm = 0;
+    int32_t um = 0, fm = 0, fl = 0;
+    bool packed = false;
 };
 
 struct CorankOpts {

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void corank_list_kernel(const int32_t *__restr
 
 // ------------------------------------------------------------ merge pass
 
-template <int NT, int VT, typename T>
+template <int NT, int VT, typename T, bool PK = false>
 __global__ __launch_bounds__(NT) void merge_pass_kernel(const int32_t *__restrict__ kin,
                                                         const int32_t *__restrict__ vin,
                                                         int32_t *__restrict__ kout,
@@ -128,18 +128,18 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(const int32_t *__restric
     for (int k = 0; k < VT; ++k) {
         const int idx = t + NT * k;
         if (idx < cnt)
-            store_elem<T>(kout, vout, o0 + idx, map_elem(S[idx], xout));
+            store_elem<T, PK>(kout, vout, o0 + idx, map_elem(S[idx], xout));
     }
 }
 
 // ------------------------------------------- persistent, pipelined merge pass
 
-template <int NT, int VT, typename T, bool BIT = false>
+template <int NT, int VT, typename T, bool BIT = false, bool PK = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(merge_waves_per_simd<T, VT>())))
 void merge_pass_pipe_kernel(PlainMap map, int64_t run, const int64_t *__restrict__ cr,
                             int xcd_group, KeyMap xout)
 {
-    merge_pipe_body<NT, VT, T, PlainMap, BIT>(map, run, cr, map.n, xcd_group, xout);
+    merge_pipe_body<NT, VT, T, PlainMap, BIT, PK>(map, run, cr, map.n, xcd_group, xout);
 }
 
 // ------------------------------------------------------------- launchers
@@ -198,6 +198,15 @@ static hipError_t launch_mp(const int32_t *kin, const int32_t *vin, int32_t *kou
                             int64_t n, int64_t run, const int64_t *cr, hipStream_t s, KeyMap xout)
 {
     const int64_t ntiles = (n + NT * VT - 1) / (NT * VT);
+    if constexpr (sizeof(T) == 8) {
+        if (xout.packed) {
+            hipLaunchKernelGGL((merge_pass_kernel<NT, VT, T, true>), dim3((unsigned)ntiles),
+                               dim3(NT), 0, s, kin, vin, kout, vout, n, run, cr, xout);
+            return hipGetLastError();
+        }
+    } else if (xout.packed) {
+        return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL((merge_pass_kernel<NT, VT, T>), dim3((unsigned)ntiles), dim3(NT), 0, s,
                        kin, vin, kout, vout, n, run, cr, xout);
     return hipGetLastError();
@@ -219,16 +228,17 @@ int device_cus()
     return cus[dev];
 }
 
-template <int NT, int VT, typename T, bool BIT = false>
-static hipError_t launch_mpp(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
-                             int64_t n, int64_t run, const int64_t *cr, int occupancy, bool xcd,
-                             hipStream_t s, KeyMap xout)
+template <int NT, int VT, typename T, bool BIT = false, bool PK = false>
+static hipError_t launch_mpp1(const int32_t *kin, const int32_t *vin, int32_t *kout,
+                              int32_t *vout, int64_t n, int64_t run, const int64_t *cr,
+                              int occupancy, bool xcd, hipStream_t s, KeyMap xout)
 {
     const int64_t ntiles = (n + NT * VT - 1) / (NT * VT);
     int occ = occupancy;
     if (occ <= 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &occ, (const void *)merge_pass_pipe_kernel<NT, VT, T, BIT>, NT, 0) != hipSuccess ||
+                &occ, (const void *)merge_pass_pipe_kernel<NT, VT, T, BIT, PK>, NT, 0) !=
+                hipSuccess ||
             occ <= 0)
             occ = 1;
     }
@@ -244,9 +254,26 @@ static hipError_t launch_mpp(const int32_t *kin, const int32_t *vin, int32_t *ko
     map.ov = vout;
     map.n = n;
     map.ntiles = ntiles;
-    hipLaunchKernelGGL((merge_pass_pipe_kernel<NT, VT, T, BIT>), dim3((unsigned)grid), dim3(NT), 0, s,
-                       map, run, cr, xcd ? 1 : 0, xout);
+    hipLaunchKernelGGL((merge_pass_pipe_kernel<NT, VT, T, BIT, PK>), dim3((unsigned)grid), dim3(NT),
+                       0, s, map, run, cr, xcd ? 1 : 0, xout);
     return hipGetLastError();
+}
+
+// xout.packed (the last pass of a 64-bit key sort) selects the instance that
+// stores packed 64-bit elements
+template <int NT, int VT, typename T, bool BIT = false>
+static hipError_t launch_mpp(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
+                             int64_t n, int64_t run, const int64_t *cr, int occupancy, bool xcd,
+                             hipStream_t s, KeyMap xout)
+{
+    if constexpr (sizeof(T) == 8) {
+        if (xout.packed)
+            return launch_mpp1<NT, VT, T, BIT, true>(kin, vin, kout, vout, n, run, cr, occupancy,
+                                                     xcd, s, xout);
+    } else if (xout.packed) {
+        return hipErrorInvalidValue;
+    }
+    return launch_mpp1<NT, VT, T, BIT>(kin, vin, kout, vout, n, run, cr, occupancy, xcd, s, xout);
 }
 
 hipError_t launch_merge_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
@@ -257,7 +284,8 @@ hipError_t launch_merge_pass(int tm, bool pairs, const int32_t *kin, const int32
     // The pipelined kernel moves 16-byte chunks: it needs 16-byte aligned
     // arrays and at least 16 elements; anything else takes the simple kernel.
     const bool aligned = ((uintptr_t)kin % 16 == 0) && ((uintptr_t)kout % 16 == 0) &&
-                         (!pairs || (((uintptr_t)vin % 16 == 0) && ((uintptr_t)vout % 16 == 0)));
+                         (!pairs || (((uintptr_t)vin % 16 == 0) &&
+                                     (xout.packed || (uintptr_t)vout % 16 == 0)));
     if (variant == 4 && !pairs && aligned && n >= 16) {  // bitonic register merge (keys)
         switch (tm) {
         case 2048:

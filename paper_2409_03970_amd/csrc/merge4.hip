@@ -309,7 +309,9 @@ __device__ __forceinline__ Tile4 tile4_geo(const Group<T> &G, int64_t run, int64
     return t;
 }
 
-template <int NT, int VT, typename T>
+// PK: the output is one packed 64-bit array at kout (the last pass of a
+// 64-bit key sort).
+template <int NT, int VT, typename T, bool PK = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void merge4_pipe_kernel(const int32_t *__restrict__ kin,
                                                          const int32_t *__restrict__ vin,
                                                          int32_t *__restrict__ kout,
@@ -457,7 +459,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
         // coalesced; a tile starts at a multiple of TM, so 16-byte aligned
         put_row<VT>(MX, diag, out, cur.cnt - diag);
         lds_barrier();
-        copy_out<NT, CH, T>(MX, kout, vout, cur.gb + cur.o0, cur.cnt, t);
+        copy_out<NT, CH, T, PK>(MX, kout, vout, cur.gb + cur.o0, cur.cnt, t);
         if (!more)
             break;
         g = gn;
@@ -485,24 +487,39 @@ static hipError_t launch_quad_corank(const int32_t *kin, const int32_t *vin, int
     return hipGetLastError();
 }
 
-template <int NT, int VT, typename T>
-static hipError_t launch_m4(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
-                            int64_t n, int64_t run, const void *rec, int occupancy, hipStream_t s,
-                            KeyMap xout)
+template <int NT, int VT, typename T, bool PK>
+static hipError_t launch_m4_1(const int32_t *kin, const int32_t *vin, int32_t *kout,
+                              int32_t *vout, int64_t n, int64_t run, const void *rec,
+                              int occupancy, hipStream_t s, KeyMap xout)
 {
     const int64_t ntiles = (n + NT * VT - 1) / (NT * VT);
     int occ = occupancy;
     if (occ <= 0 &&
-        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)merge4_pipe_kernel<NT, VT, T>,
-                                                      NT, 0) != hipSuccess ||
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+             &occ, (const void *)merge4_pipe_kernel<NT, VT, T, PK>, NT, 0) != hipSuccess ||
          occ <= 0))
         occ = 1;
     int64_t grid = (int64_t)device_cus() * occ;
     if (grid > ntiles)
         grid = ntiles;
-    hipLaunchKernelGGL((merge4_pipe_kernel<NT, VT, T>), dim3((unsigned)grid), dim3(NT), 0, s, kin,
-                       vin, kout, vout, n, run, (const Quad *)rec, ntiles, xout);
+    hipLaunchKernelGGL((merge4_pipe_kernel<NT, VT, T, PK>), dim3((unsigned)grid), dim3(NT), 0, s,
+                       kin, vin, kout, vout, n, run, (const Quad *)rec, ntiles, xout);
     return hipGetLastError();
+}
+
+template <int NT, int VT, typename T>
+static hipError_t launch_m4(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
+                            int64_t n, int64_t run, const void *rec, int occupancy, hipStream_t s,
+                            KeyMap xout)
+{
+    if constexpr (sizeof(T) == 8) {
+        if (xout.packed)
+            return launch_m4_1<NT, VT, T, true>(kin, vin, kout, vout, n, run, rec, occupancy, s,
+                                                xout);
+    } else if (xout.packed) {
+        return hipErrorInvalidValue;
+    }
+    return launch_m4_1<NT, VT, T, false>(kin, vin, kout, vout, n, run, rec, occupancy, s, xout);
 }
 
 hipError_t launch_merge4_corank(int tm, bool pairs, const int32_t *kin, const int32_t *vin,

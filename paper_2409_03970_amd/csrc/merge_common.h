@@ -364,7 +364,7 @@ template <typename T> __device__ __forceinline__ void put_chunk(T *S, int c, con
 // 16-byte aligned.
 // Coalesced copy of the first cnt elements of a skewed LDS array to global
 // index abs0 (a multiple of 4): thread t moves 16-byte chunks t, t + NT, ...
-template <int NT, int CH, typename T>
+template <int NT, int CH, typename T, bool PK = false>
 __device__ __forceinline__ void copy_out(const LdsSkew<T> &W, int32_t *__restrict__ k,
                                          int32_t *__restrict__ v, int64_t abs0, int cnt, int t)
 {
@@ -380,6 +380,11 @@ __device__ __forceinline__ void copy_out(const LdsSkew<T> &W, int32_t *__restric
             if constexpr (sizeof(T) == 4) {
                 // one 16-byte copy (W[4c] is 16-byte aligned in the skewed layout)
                 *(int4 *)(k + e) = *(const int4 *)&W[4 * c];
+            } else if constexpr (PK) {
+                typedef int64_t V2 __attribute__((ext_vector_type(2)));
+                V2 *o = (V2 *)((int64_t *)k + e);
+                o[0] = *(const V2 *)&W[4 * c];
+                o[1] = *(const V2 *)&W[4 * c + 2];
             } else {
                 T x[4];
 #pragma unroll
@@ -398,7 +403,7 @@ __device__ __forceinline__ void copy_out(const LdsSkew<T> &W, int32_t *__restric
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (4 * c + u < cnt)
-                    store_elem<T>(k, v, e + u, W[4 * c + u]);
+                    store_elem<T, PK>(k, v, e + u, W[4 * c + u]);
         }
     }
 }
@@ -414,8 +419,9 @@ template <typename T, int VT> constexpr int merge_waves_per_simd()
 
 // BIT: each thread merges its merge-path share with the bitonic network in
 // registers (reg_merge) instead of the serial merge (the two mergers of
-// Table 3; the serial one is the default).
-template <int NT, int VT, typename T, typename Map, bool BIT = false>
+// Table 3; the serial one is the default).  PK: the output is one packed
+// 64-bit array at the key pointer (the last pass of a 64-bit key sort).
+template <int NT, int VT, typename T, typename Map, bool BIT = false, bool PK = false>
 __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
                                                 const int64_t *__restrict__ cr, int64_t n_abs,
                                                 int xcd_group, KeyMap xout = {})
@@ -558,6 +564,16 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
             if (4 * c >= cur.shift && 4 * c + 4 <= end) {
                 if constexpr (sizeof(T) == 4) {
                     *(int4 *)(cur.r.ok + e) = *(const int4 *)&Z[4 * c];
+                } else if constexpr (PK) {
+                    typedef int64_t V2 __attribute__((ext_vector_type(2)));
+                    V2 x0 = *(const V2 *)&Z[4 * c], x1 = *(const V2 *)&Z[4 * c + 2];
+                    if (key_map_on(xout)) {  // wave-uniform
+                        x0 = V2{map_elem(x0.x, xout), map_elem(x0.y, xout)};
+                        x1 = V2{map_elem(x1.x, xout), map_elem(x1.y, xout)};
+                    }
+                    V2 *o = (V2 *)((int64_t *)cur.r.ok + e);
+                    o[0] = x0;
+                    o[1] = x1;
                 } else {
                     const T x0 = Z[4 * c], x1 = Z[4 * c + 1], x2 = Z[4 * c + 2], x3 = Z[4 * c + 3];
                     int4 kk = make_int4(pair_key(x0), pair_key(x1), pair_key(x2), pair_key(x3));
@@ -572,9 +588,9 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
 #pragma unroll
                 for (int q2 = 0; q2 < 4; ++q2)
                     if (4 * c + q2 >= cur.shift && 4 * c + q2 < end)
-                        store_elem<T>(cur.r.ok, cur.r.ov, e + q2,
-                                      sizeof(T) == 8 ? map_elem(Z[4 * c + q2], xout)
-                                                     : Z[4 * c + q2]);
+                        store_elem<T, PK>(cur.r.ok, cur.r.ov, e + q2,
+                                          sizeof(T) == 8 ? map_elem(Z[4 * c + q2], xout)
+                                                         : Z[4 * c + q2]);
             }
         }
         if (!more)

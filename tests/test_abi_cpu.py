@@ -26,7 +26,7 @@ def _declared():
 
 def test_every_declared_symbol_is_exported():
     names = _declared()
-    assert len(names) == 23
+    assert len(names) == 27
     L = hv.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -60,6 +60,12 @@ def test_workspace_queries():
     o = hv.Options(keys_per_lane=7)
     assert L.hvms_sort_workspace_bytes(1000, 0, ctypes.byref(o)) == -4
     assert L.hvms_merge_workspace_bytes(1 << 20, 4096, None) > 0
+    # 64-bit keys: two split buffer pairs (16 bytes per key) plus co-ranks
+    w64 = L.hvms_sort64_workspace_bytes(1 << 20, None)
+    assert w64 >= 16 * (1 << 20) and w64 % 256 == 0
+    assert w64 > L.hvms_sort_workspace_bytes(1 << 20, 1, None)
+    assert L.hvms_sort64_workspace_bytes(100, None) == 0
+    assert L.hvms_sort64_workspace_bytes(-1, None) == -1
 
 
 def test_argument_errors_before_any_launch():
@@ -88,6 +94,14 @@ def test_argument_errors_before_any_launch():
     for f in (L.hvms_sort_pairs_u32, L.hvms_sort_pairs_f32):
         assert f(FAKE, None, FAKE, FAKE, 3, None, 0, None, None) == -1
         assert f(FAKE, FAKE, FAKE, FAKE, 1 << 20, FAKE, 16, None, None) == -2
+    for f in (L.hvms_sort_i64, L.hvms_sort_u64, L.hvms_sort_f64):
+        assert f(None, FAKE, 5, None, 0, None, None) == -1
+        assert f(FAKE, FAKE, 0, None, 0, None, None) == 0
+        assert f(FAKE, ctypes.c_void_p(0x100004), 5, None, 0, None, None) == -1   # not 8-aligned
+        assert f(FAKE, FAKE, 1 << 20, None, 0, None, None) == -2
+        assert f(FAKE, FAKE, 1 << 20, FAKE, 16, None, None) == -2
+        assert f(FAKE, FAKE, 10, None, 0, None, ctypes.byref(bad)) == -4
+        assert f(FAKE, FAKE, 10, None, 0, None, ctypes.byref(v4)) == -4       # keys-only merger
     assert L.hvms_sort_runs_i32(FAKE, FAKE, 100, 2, None, None) == -1        # run below R
     assert L.hvms_sort_runs_i32(FAKE, FAKE, 100, 20, None, None) == -1       # run above tile
     assert L.hvms_merge_pass_i32(FAKE, FAKE, 100, 3000, None, 0, None, None) == -1  # not 2^k

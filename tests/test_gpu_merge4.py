@@ -68,3 +68,28 @@ def test_four_way_full_size():
     for p in [0, n // 3, n - 1]:
         lt, le = oracle.count(xs, ys[p])
         assert lt <= p < le
+
+
+@pytest.mark.parametrize("offset", [1, 2, 3])
+def test_four_way_requested_with_unaligned_output(offset):
+    # an output that is not 16-byte aligned takes two-way passes (the
+    # four-way kernel moves 16-byte chunks of the arrays it writes)
+    n = 1_000_003
+    x = inputs.keys(n, "uniform", seed=7 + offset, device=DEV)
+    big = torch.empty(n + offset, dtype=torch.int32, device=DEV)
+    y = big[offset:]
+    assert y.data_ptr() % 16 != 0
+    opts = {"merge_ways": 4, "merge_tile": 8192}
+    ws = hv._workspace(hv.lib().hvms_sort_workspace_bytes(n, 0, hv._opts(opts)), x.device)
+    hv.hvms_sort_i32(x, y, ws, opts=opts)
+    assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy()))
+    k = inputs.keys(n, "distinct16", seed=8, device=DEV)
+    v = torch.randint(-5, 5, (n,), device=DEV, dtype=torch.int32)
+    vbig = torch.empty(n + offset, dtype=torch.int32, device=DEV)
+    popts = {"merge_ways": 4, "merge_tile": 4096}
+    ws = hv._workspace(hv.lib().hvms_sort_workspace_bytes(n, 1, hv._opts(popts)), x.device)
+    ko = torch.empty_like(k)
+    hv.hvms_sort_pairs_i32(k, v, ko, vbig[offset:], ws, opts=popts)
+    ek, ev = oracle.sort_pairs(k.cpu().numpy(), v.cpu().numpy())
+    assert np.array_equal(ko.cpu().numpy(), ek)
+    assert np.array_equal(vbig[offset:].cpu().numpy(), ev)

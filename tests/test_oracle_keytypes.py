@@ -1,7 +1,8 @@
-"""Pins of the oracle's uint32 and float32 sorts: numpy's sort where its
-order is the same (unsigned integers; finite nonzero floats), the IEEE 754
-totalOrder sequence of special values (tests/golden/f32_total_order.txt),
-and lexicographic pair order against numpy's lexsort."""
+"""Pins of the oracle's uint32, float32, int64, uint64 and float64 sorts:
+numpy's sort where its order is the same (integers; finite nonzero floats),
+the IEEE 754 totalOrder sequences of special values
+(tests/golden/f32_total_order.txt, f64_total_order.txt), and lexicographic
+pair order against numpy's lexsort."""
 import numpy as np
 import pytest
 
@@ -78,3 +79,71 @@ def test_pairs_f32_signed_zeros_order_by_sign_first():
     ko, vo = oracle.sort_pairs_f32(k, v)
     assert list(ko.view(np.uint32) >> 31) == [1, 1, 0, 0]
     assert list(vo) == [-2, 2, -1, 1]
+
+
+# ------------------------------------------------------------- 64-bit keys
+
+def _golden64(golden_dir):
+    rows = []
+    with open(f"{golden_dir}/f64_total_order.txt") as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append(int(line.split()[0], 16))
+    return np.array(rows, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 9, 1000, 100003])
+def test_i64_matches_numpy(n):
+    rng = np.random.default_rng(100 + n)
+    x = rng.integers(-2**63, 2**63, size=n, dtype=np.int64)
+    # extremes, and keys equal in the high word that differ in the low word
+    # (with the low word's top bit set and clear)
+    special = np.array([-2**63, 2**63 - 1, -1, 0, 1, 2**31, 2**32 - 1, 2**32,
+                        -2**32, -2**32 + 2**31, 5 * 2**32 + 2**31, 5 * 2**32 + 7], dtype=np.int64)
+    x[: n // 5] = rng.choice(special, size=n // 5)
+    assert np.array_equal(oracle.sort_i64(x), np.sort(x))
+
+
+@pytest.mark.parametrize("n", [1, 7, 1000, 100003])
+def test_u64_matches_numpy(n):
+    rng = np.random.default_rng(200 + n)
+    x = rng.integers(0, 2**64, size=n, dtype=np.uint64)
+    special = np.array([0, 1, 2**63 - 1, 2**63, 2**64 - 1, 2**32, 2**63 + 2**31],
+                       dtype=np.uint64)
+    x[: n // 5] = rng.choice(special, size=n // 5)
+    got = oracle.sort_u64(x)
+    assert np.array_equal(got, np.sort(x))
+    if n > 5:  # keys with the top bit set go last (a signed compare would put them first)
+        assert got[-1] >= np.uint64(2**63) or not (x >= np.uint64(2**63)).any()
+
+
+def test_i64_and_u64_orders_differ_on_top_bit():
+    x = np.array([2**63, 1, 2**63 + 5, 3], dtype=np.uint64)
+    assert list(oracle.sort_u64(x)) == [1, 3, 2**63, 2**63 + 5]
+    assert list(oracle.sort_i64(x.view(np.int64)).view(np.uint64)) == [2**63, 2**63 + 5, 1, 3]
+
+
+@pytest.mark.parametrize("n", [1, 5, 4097, 100003])
+def test_f64_finite_nonzero_matches_numpy(n):
+    rng = np.random.default_rng(300 + n)
+    x = rng.standard_normal(n) * 10.0 ** rng.integers(-300, 300, size=n)
+    x[x == 0] = 1.0
+    got = oracle.sort_f64(x)
+    assert np.array_equal(got.view(np.uint64), np.sort(x).view(np.uint64))
+
+
+def test_f64_special_values_follow_total_order(golden_dir):
+    want = _golden64(golden_dir)
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        x = rng.permutation(np.repeat(want, 3))
+        got = oracle.sort_f64(x.view(np.float64)).view(np.uint64)
+        assert np.array_equal(got, np.repeat(want, 3))
+
+
+def test_f64_golden_finite_values_ascend(golden_dir):
+    # the fixture's finite entries, read as numbers, ascend (ties only at the
+    # two zeros), which checks the fixture itself against arithmetic order
+    want = _golden64(golden_dir).view(np.float64)
+    fin = want[np.isfinite(want)]
+    assert (np.diff(fin) >= 0).all() and (np.diff(fin) == 0).sum() == 1
