@@ -135,7 +135,8 @@ def four_way_bench(x, ref_out, opts):
 def key_types_bench(n):
     """uint32 and float32 keys (tuned sort options) against int32 on the
     same number of keys; the key map is fused into the first and last
-    launches, so the rates should match."""
+    launches, so the rates should match.  Then int64, uint64 and float64
+    keys (tuned key-value options: 64-bit keys run on those kernels)."""
     dev = torch.device("cuda", 0)
     from paper_2409_03970_amd import tune
     opts = tune.tuned_options("sort", n) or {}
@@ -157,6 +158,39 @@ def key_types_bench(n):
     ms = _median_ms(lambda: hv.hvms_sort_f32(f, fo, ws, opts=opts))
     res["float32"] = {"ms": round(ms, 3), "gkeys_per_s": round(n / ms / 1e6, 3),
                       "sorted": bool((fo[1:] >= fo[:-1]).all())}
+    del ws, bits, out, f, fo
+    torch.cuda.empty_cache()
+    # 64-bit keys run on the key-value kernels (16 bytes per key per pass)
+    o64 = tune.tuned_options("sort_pairs", n) or {}
+    tile = (o64.get("keys_per_lane") or 16) * (o64.get("block_threads") or 512)
+    passes = merge_passes(n, tile, o64.get("merge_ways") or 2)
+    ws = hv._workspace(hv.lib().hvms_sort64_workspace_bytes(n, hv._opts(o64)), dev)
+    x = torch.randint(-2**63, 2**63 - 1, (n,), dtype=torch.int64, device=dev, generator=g)
+    y = torch.empty_like(x)
+    for name, fn, xv, yv in (("int64", hv.hvms_sort_i64, x, y),
+                             ("uint64", hv.hvms_sort_u64, x.view(torch.uint64),
+                              y.view(torch.uint64)),
+                             ("float64", hv.hvms_sort_f64, None, None)):
+        if name == "float64":
+            del x, y
+            xv = torch.randn(n, dtype=torch.float64, device=dev, generator=g) * 1e3
+            xv[xv == 0] = 1.0
+            yv = torch.empty_like(xv)
+        ms = _median_ms(lambda: fn(xv, yv, ws, opts=o64))
+        ev = make_events(2 + 2 * passes)
+        fn(xv, yv, ws, opts=dict(o64, events=ev))
+        torch.cuda.synchronize()
+        pm = [ev[2 + 2 * p].elapsed_time(ev[3 + 2 * p]) for p in range(passes)]
+        mono = yv.view(torch.int64)
+        if name == "uint64":
+            mono = mono ^ (-2**63)                    # unsigned order as signed
+        elif name == "float64":
+            mono = yv
+        res[name] = {"ms": round(ms, 3), "gkeys_per_s": round(n / ms / 1e6, 3),
+                     "merge_pass_gbs_mean": round(16.0 * n / (np.mean(pm) / 1e3) / 1e9, 1)
+                     if pm else None,
+                     "sorted": bool((mono[1:] >= mono[:-1]).all())}
+    res["options_64bit"] = o64
     return res
 
 
@@ -258,6 +292,25 @@ def pairs_bench(n):
     ok = bool((ko[1:] >= ko[:-1]).all()) and bool(torch.equal(k[vo.long()], ko))
     return {"ms": round(ms, 3), "gkeys_per_s": round(n / ms / 1e6, 3), "options": opts,
             "merge_pass_gbs_mean": round(16.0 * n / (np.mean(pm) / 1e3) / 1e9, 1) if pm else None,
+            "certificate_ok": ok}
+
+
+def by_key_bench(n):
+    """Stable sort of 2^28 uniform int32 keys carrying 64-bit payloads (the
+    payload is the input index, which makes the certificate cheap)."""
+    dev = torch.device("cuda", 0)
+    k = inputs.keys(n, "uniform", seed=0, device=dev)
+    v = torch.arange(n, dtype=torch.int64, device=dev)
+    ko, vo = torch.empty_like(k), torch.empty_like(v)
+    from paper_2409_03970_amd import tune
+    opts = tune.tuned_options("sort_pairs", n) or {}
+    ws = hv._workspace(hv.lib().hvms_sort_by_key_workspace_bytes(n, hv._opts(opts)), dev)
+    ms = _median_ms(lambda: hv.hvms_sort_by_key_i32_p64(k, v, ko, vo, ws, opts=opts))
+    # certificate: keys nondecreasing, each payload still points at its key,
+    # and equal keys keep their input order
+    ok = (bool((ko[1:] >= ko[:-1]).all()) and bool(torch.equal(k[vo], ko))
+          and bool(((ko[1:] > ko[:-1]) | (vo[1:] > vo[:-1])).all()))
+    return {"ms": round(ms, 3), "gkeys_per_s": round(n / ms / 1e6, 3), "options": opts,
             "certificate_ok": ok}
 
 
@@ -687,6 +740,7 @@ def main():
         extras = (("in_register_sort_table2", table2_bench),
                   ("merge_table3", lambda: merge_table3_bench(n)),
                   ("pairs_2p28", lambda: pairs_bench(n)),
+                  ("sort_by_key_p64_2p28", lambda: by_key_bench(n)),
                   ("batched_learned_pairs_50k_segments", config5_bench if args.all else None),
                   ("batched_200k_segments", batched_bench),
                   ("learned_2p30_mixture", learned_bench),

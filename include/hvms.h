@@ -198,6 +198,29 @@ int hvms_sort_f64(const double *d_in, double *d_out, int64_t n, void *d_ws,
                   size_t ws_bytes, void *stream, const hvms_options *opt);
 
 /*
+ * 64-bit payloads: a stable sort of int32 keys carrying one 64-bit value each
+ * (any 8-byte type: int64, uint64, double, a pointer).  d_keys_out is the
+ * ascending arrangement of d_keys_in; d_vals_out[i] is the payload that
+ * came with d_keys_out[i]; keys that are equal keep their input order.  The
+ * keys are sorted together with their input indices by the key-value sort
+ * (indices made in the block stage, never read from memory), then one pass
+ * moves the payloads: d_vals_out[i] = d_vals_in[index[i]].
+ *   d_keys_in/out   device int32 arrays of n elements (may be equal).
+ *   d_vals_in/out   device arrays of n 64-bit elements, 8-byte aligned, not
+ *                   overlapping (else HVMS_ERR_INVALID_ARG).
+ *   n               0 <= n <= 2^31 - 1 (indices are int32).
+ *   d_ws/ws_bytes   workspace, >= hvms_sort_by_key_workspace_bytes(n, opt)
+ *                   (4 bytes per key for the indices plus the key-value
+ *                   sort's workspace), 256-byte aligned.
+ * Tuning values are those of hvms_sort_pairs_i32.  n == 0 is a no-op.
+ */
+int64_t hvms_sort_by_key_workspace_bytes(int64_t n, const hvms_options *opt);
+int hvms_sort_by_key_i32_p64(const int32_t *d_keys_in, const uint64_t *d_vals_in,
+                             int32_t *d_keys_out, uint64_t *d_vals_out, int64_t n,
+                             void *d_ws, size_t ws_bytes, void *stream,
+                             const hvms_options *opt);
+
+/*
  * Sort every run of 2^run_log2 consecutive keys independently (the last run
  * may be shorter): the block stage alone, i.e. "every X elements in order"
  * of Table 2 with X = 2^run_log2.  run_log2 must lie in

@@ -43,6 +43,7 @@ def lib():
         _u64p = ctypes.POINTER(ctypes.c_uint64)
         for name in ("oracle_sort_i64", "oracle_sort_u64", "oracle_sort_f64"):
             getattr(L, name).argtypes = [_u64p, ctypes.c_int64]
+        L.oracle_sort_by_key_i32_p64.argtypes = [_i32p, _u64p, ctypes.c_int64]
         for name in ("oracle_sort_pairs_u32", "oracle_sort_pairs_f32"):
             getattr(L, name).argtypes = [_u32p, _i32p, ctypes.c_int64]
         L.oracle_segmented_sort_i32.argtypes = [_i32p, _i64p, ctypes.c_int64]
@@ -141,6 +142,19 @@ def sort_f64(keys):
     """Sorted copy of float64 keys in IEEE 754 totalOrder (bit-exact: -0
     before +0, NaNs placed by sign and payload)."""
     return _sort64(lib().oracle_sort_f64, keys, np.float64)
+
+
+def sort_by_key_p64(keys, vals):
+    """Stable sort by int32 key carrying 64-bit payloads (any 8-byte dtype):
+    copies (keys, vals) with keys nondecreasing, equal keys in input order."""
+    k, pk = _i32(np.array(keys, dtype=np.int32, copy=True))
+    v0 = np.array(vals, copy=True)
+    assert v0.dtype.itemsize == 8 and v0.size == k.size
+    v = np.ascontiguousarray(v0.view(np.uint64))
+    if lib().oracle_sort_by_key_i32_p64(pk, v.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                        k.size) != 0:
+        raise MemoryError("oracle sort by key failed")
+    return k, v.view(v0.dtype)
 
 
 def _sort_pairs_gen(fn, a, vals):

@@ -19,6 +19,8 @@
  *   - other key types: the same with the type's own order (uint32/uint64
  *                     unsigned, float32/float64 IEEE 754 totalOrder,
  *                     int64 signed);
+ *   - sort by key:    int32 keys with 64-bit payloads, keys nondecreasing,
+ *                     equal keys in input order (stable);
  *   - segmented:      the above applied to each segment independently;
  *   - co-rank:        the number of elements of A among the first d outputs
  *                     of the merge of sorted A and B that takes A first on
@@ -291,6 +293,59 @@ static int sort64(less64_fn less, uint64_t *k, int64_t n)
 int oracle_sort_i64(uint64_t *k, int64_t n) { return sort64(less_i64, k, n); }
 int oracle_sort_u64(uint64_t *k, int64_t n) { return sort64(less_u64, k, n); }
 int oracle_sort_f64(uint64_t *bits, int64_t n) { return sort64(less_f64_total, bits, n); }
+
+/* ------------------------------------------------------ 64-bit payloads */
+
+/*
+ * Stable sort by key with a 64-bit payload: the keys in nondecreasing signed
+ * order, each payload moved with its key, equal keys in their input order.
+ * The merge sort compares keys only and takes the left element on ties,
+ * which is what makes it stable.
+ */
+static void msort_bykey(int32_t *k, uint64_t *v, int32_t *auxk, uint64_t *auxv, int64_t lo,
+                        int64_t hi)
+{
+    if (hi - lo < 2)
+        return;
+    int64_t mid = lo + (hi - lo) / 2;
+    msort_bykey(k, v, auxk, auxv, lo, mid);
+    msort_bykey(k, v, auxk, auxv, mid, hi);
+    int64_t i = lo, j = mid, o = lo;
+    while (i < mid || j < hi) {
+        int take_j;
+        if (i == mid)
+            take_j = 1;
+        else if (j == hi)
+            take_j = 0;
+        else
+            take_j = k[j] < k[i];
+        int64_t src = take_j ? j++ : i++;
+        auxk[o] = k[src];
+        auxv[o] = v[src];
+        ++o;
+    }
+    memcpy(k + lo, auxk + lo, (size_t)(hi - lo) * sizeof(int32_t));
+    memcpy(v + lo, auxv + lo, (size_t)(hi - lo) * sizeof(uint64_t));
+}
+
+int oracle_sort_by_key_i32_p64(int32_t *k, uint64_t *v, int64_t n)
+{
+    if (n < 0)
+        return -1;
+    if (n < 2)
+        return 0;
+    int32_t *auxk = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    uint64_t *auxv = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    if (!auxk || !auxv) {
+        free(auxk);
+        free(auxv);
+        return -1;
+    }
+    msort_bykey(k, v, auxk, auxv, 0, n);
+    free(auxk);
+    free(auxv);
+    return 0;
+}
 
 /* ------------------------------------------------------------- segmented */
 

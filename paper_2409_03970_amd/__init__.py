@@ -23,7 +23,7 @@ __all__ = [
     "hvms_cdf_sample_i32", "cdf_sample", "fit_cdf_model", "segmented_sort_pairs_grouped",
     "segment_groups", "hvms_sort_u32", "hvms_sort_f32", "hvms_sort_pairs_u32",
     "hvms_sort_pairs_f32", "sort_keys", "sort_pairs_keys", "hvms_sort_i64", "hvms_sort_u64",
-    "hvms_sort_f64",
+    "hvms_sort_f64", "hvms_sort_by_key_i32_p64", "sort_by_key",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -82,6 +82,8 @@ _SIGS = {
     "hvms_sort_pairs_u32": ([_vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
     "hvms_sort_pairs_f32": ([_vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
     "hvms_sort64_workspace_bytes": ([_i64, _opt], _i64),
+    "hvms_sort_by_key_workspace_bytes": ([_i64, _opt], _i64),
+    "hvms_sort_by_key_i32_p64": ([_vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
     "hvms_sort_i64": ([_vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
     "hvms_sort_u64": ([_vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
     "hvms_sort_f64": ([_vp, _vp, _i64, _vp, _sz, _vp, _opt], _i32),
@@ -242,6 +244,17 @@ def hvms_sort_f64(d_in, d_out, ws=None, stream=None, opts=None):
     _sort64("hvms_sort_f64", "f64", d_in, d_out, ws, stream, opts)
 
 
+def hvms_sort_by_key_i32_p64(k_in, v_in, k_out, v_out, ws=None, stream=None, opts=None):
+    assert k_in.numel() == v_in.numel() == k_out.numel() == v_out.numel()
+    for t in (v_in, v_out):
+        if t.element_size() != 8:
+            raise ValueError(f"payloads must be 8-byte elements, got {t.dtype}")
+    p, b = _wsargs(ws)
+    _check("hvms_sort_by_key_i32_p64", lib().hvms_sort_by_key_i32_p64(
+        _ptr(k_in, torch.int32), _ptr(v_in, None), _ptr(k_out, torch.int32), _ptr(v_out, None),
+        k_in.numel(), p, b, _stream(stream), _opts(opts)))
+
+
 def _sort_pairs_mapped(fn, kind, k_in, v_in, k_out, v_out, ws, stream, opts):
     assert k_in.numel() == v_in.numel() == k_out.numel() == v_out.numel()
     p, b = _wsargs(ws)
@@ -400,6 +413,18 @@ def sort_pairs_keys(keys, vals, keys_out=None, vals_out=None, opts=None, stream=
     vals_out = torch.empty_like(vals) if vals_out is None else vals_out
     ws = _workspace(lib().hvms_sort_workspace_bytes(keys.numel(), 1, _opts(opts)), keys.device)
     fn(keys, vals, keys_out, vals_out, ws, stream, opts)
+    return keys_out, vals_out
+
+
+def sort_by_key(keys, vals, keys_out=None, vals_out=None, opts=None, stream=None):
+    """Stable sort of int32 keys carrying 64-bit payloads (vals: any 8-byte
+    dtype); equal keys keep their input order.  keys_out may be keys."""
+    opts = _auto("sort_pairs", keys.numel(), opts)
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    vals_out = torch.empty_like(vals) if vals_out is None else vals_out
+    ws = _workspace(lib().hvms_sort_by_key_workspace_bytes(keys.numel(), _opts(opts)),
+                    keys.device)
+    hvms_sort_by_key_i32_p64(keys, vals, keys_out, vals_out, ws, stream, opts)
     return keys_out, vals_out
 
 

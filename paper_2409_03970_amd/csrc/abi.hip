@@ -402,6 +402,52 @@ int hvms_sort_f64(const double *d_in, double *d_out, int64_t n, void *d_ws, size
     return sort_keys64(d_in, d_out, n, d_ws, ws_bytes, stream, opt, 2);
 }
 
+int64_t hvms_sort_by_key_workspace_bytes(int64_t n, const hvms_options *opt)
+{
+    Cfg c;
+    if (n < 0)
+        return HVMS_ERR_INVALID_ARG;
+    const int st = resolve(opt, true, c);
+    if (st)
+        return st;
+    if (n == 0)
+        return 0;
+    return align256(n * 4) + sort_ws_layout(n, true, c).total;
+}
+
+int hvms_sort_by_key_i32_p64(const int32_t *d_keys_in, const uint64_t *d_vals_in,
+                             int32_t *d_keys_out, uint64_t *d_vals_out, int64_t n, void *d_ws,
+                             size_t ws_bytes, void *stream, const hvms_options *opt)
+{
+    if (n < 0 || n > INT32_MAX ||
+        (n > 0 && (!d_keys_in || !d_vals_in || !d_keys_out || !d_vals_out)))
+        return HVMS_ERR_INVALID_ARG;
+    if (n > 0 && (((uintptr_t)d_vals_in | (uintptr_t)d_vals_out) & 7))
+        return HVMS_ERR_INVALID_ARG;
+    // the payload pass reads d_vals_in in permuted order: no overlap allowed
+    const uintptr_t vi = (uintptr_t)d_vals_in, vo = (uintptr_t)d_vals_out;
+    if (n > 0 && vi < vo + (uintptr_t)n * 8 && vo < vi + (uintptr_t)n * 8)
+        return HVMS_ERR_INVALID_ARG;
+    Cfg c;
+    int st = resolve(opt, true, c);
+    if (st)
+        return st;
+    if (n == 0)
+        return HVMS_OK;
+    const int64_t idx_bytes = align256(n * 4);
+    st = check_ws(d_ws, ws_bytes, idx_bytes + sort_ws_layout(n, true, c).total);
+    if (st)
+        return st;
+    int32_t *idx = (int32_t *)d_ws;
+    KeyMap km;
+    km.iota = true;
+    st = run_sort(true, d_keys_in, nullptr, d_keys_out, idx, n, (char *)d_ws + idx_bytes,
+                  (hipStream_t)stream, c, km);
+    if (st)
+        return st;
+    return hip_status(launch_gather_u64(idx, d_vals_in, d_vals_out, n, (hipStream_t)stream));
+}
+
 int hvms_sort_u32(const uint32_t *d_in, uint32_t *d_out, int64_t n, void *d_ws, size_t ws_bytes,
                   void *stream, const hvms_options *opt)
 {

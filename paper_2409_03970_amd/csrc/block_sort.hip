@@ -13,7 +13,8 @@
 //       serial merge from its co-rank;
 // then the tile is written back with coalesced stores.  Ragged tiles are
 // padded with the maximum of the order.  PKM (64-bit elements only): bit 0,
-// the input is one packed 64-bit array at kin; bit 1, so is the output.
+// the input is one packed 64-bit array at kin; bit 1, so is the output;
+// bit 2, each value is the element's input index (vin is not read).
 #include "common.h"
 #include "hvms_internal.h"
 
@@ -28,7 +29,7 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
                                                         bool blocked, KeyMap xin, KeyMap xout)
 {
     constexpr int TILE = R * NT;
-    constexpr bool PI = (PKM & 1) != 0, PO = (PKM & 2) != 0;
+    constexpr bool PI = (PKM & 1) != 0, PO = (PKM & 2) != 0, IO = (PKM & 4) != 0;
     __shared__ __attribute__((aligned(16))) T S[LdsSkew<T>::size(TILE)];
     const LdsSkew<T> Z{S, 0};
     const int t = threadIdx.x;
@@ -45,7 +46,8 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int64_t g = tile0 + t + NT * j;
-            Z[t + NT * j] = g < n ? map_elem(load_elem<T, PI>(kin, vin, g), xin) : Traits<T>::kMax;
+            Z[t + NT * j] =
+                g < n ? map_elem(load_elem<T, PI, IO>(kin, vin, g), xin) : Traits<T>::kMax;
         }
         __syncthreads();
         const LdsSkew<T> W{S, wave * (64 * R) + lane * R};
@@ -56,7 +58,7 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
     } else if (tile0 + TILE <= n) {
 #pragma unroll
         for (int j = 0; j < R; ++j)
-            v[j] = load_elem<T, PI>(kin, vin, wave0 + 64 * j + lane);
+            v[j] = load_elem<T, PI, IO>(kin, vin, wave0 + 64 * j + lane);
         if (key_map_on(xin)) {  // wave-uniform
 #pragma unroll
             for (int j = 0; j < R; ++j)
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int64_t g = wave0 + 64 * j + lane;
-            v[j] = g < n ? map_elem(load_elem<T, PI>(kin, vin, g), xin) : Traits<T>::kMax;
+            v[j] = g < n ? map_elem(load_elem<T, PI, IO>(kin, vin, g), xin) : Traits<T>::kMax;
         }
     }
 
@@ -102,27 +104,31 @@ static hipError_t launch_bs1(const int32_t *kin, const int32_t *vin, int32_t *ko
 }
 
 // Packed 64-bit arrays: a packed input with split output (the block stage
-// of a longer sort) or packed on both sides (a sort of one tile).
+// of a longer sort) or packed on both sides (a sort of one tile).  Index
+// values: the block stage of a stable sort by key.
 template <int R, int NT, typename T, int NET = 0>
 static hipError_t launch_bs(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
                             int64_t n, int wave_levels, int lds_levels, bool blocked,
                             hipStream_t s, KeyMap xin, KeyMap xout)
 {
+    const int pkm = (xin.packed ? 1 : 0) | (xout.packed ? 2 : 0) | (xin.iota ? 4 : 0);
+    if (pkm == 0)
+        return launch_bs1<R, NT, T, NET>(kin, vin, kout, vout, n, wave_levels, lds_levels,
+                                         blocked, s, xin, xout);
     if constexpr (sizeof(T) == 8) {
-        if (xin.packed || xout.packed) {
-            if (!xin.packed)
-                return hipErrorInvalidValue;
-            return xout.packed
-                       ? launch_bs1<R, NT, T, NET, 3>(kin, vin, kout, vout, n, wave_levels,
-                                                      lds_levels, blocked, s, xin, xout)
-                       : launch_bs1<R, NT, T, NET, 1>(kin, vin, kout, vout, n, wave_levels,
-                                                      lds_levels, blocked, s, xin, xout);
+        switch (pkm) {
+        case 1:
+            return launch_bs1<R, NT, T, NET, 1>(kin, vin, kout, vout, n, wave_levels, lds_levels,
+                                                blocked, s, xin, xout);
+        case 3:
+            return launch_bs1<R, NT, T, NET, 3>(kin, vin, kout, vout, n, wave_levels, lds_levels,
+                                                blocked, s, xin, xout);
+        case 4:
+            return launch_bs1<R, NT, T, NET, 4>(kin, vin, kout, vout, n, wave_levels, lds_levels,
+                                                blocked, s, xin, xout);
         }
-    } else if (xin.packed || xout.packed) {
-        return hipErrorInvalidValue;
     }
-    return launch_bs1<R, NT, T, NET>(kin, vin, kout, vout, n, wave_levels, lds_levels, blocked, s,
-                                     xin, xout);
+    return hipErrorInvalidValue;
 }
 
 bool block_sort_supported(int R, int NT, bool pairs)

@@ -35,8 +35,9 @@ __device__ __forceinline__ int32_t pair_val(int64_t p)
 }
 
 // Element i of a key array, or of a key/value array pair, as type T.  PK:
-// the 64-bit elements sit packed at k (a 64-bit key array; v unused).
-template <typename T, bool PK = false>
+// the 64-bit elements sit packed at k (a 64-bit key array; v unused).  IOTA:
+// the value is the index i itself (v unused; i < 2^31).
+template <typename T, bool PK = false, bool IOTA = false>
 __device__ __forceinline__ T load_elem(const int32_t *__restrict__ k,
                                        const int32_t *__restrict__ v, int64_t i)
 {
@@ -44,6 +45,8 @@ __device__ __forceinline__ T load_elem(const int32_t *__restrict__ k,
         return k[i];
     else if constexpr (PK)
         return ((const int64_t *)k)[i];
+    else if constexpr (IOTA)
+        return pack_pair(k[i], (int32_t)i);
     else
         return pack_pair(k[i], v[i]);
 }

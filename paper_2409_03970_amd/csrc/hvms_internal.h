@@ -24,9 +24,11 @@ void set_last_hip_error(int e);
 // packed: the array on that side holds 64-bit elements at the key pointer
 // (an int64 / uint64 / float64 key array) instead of separate key and value
 // int32 arrays; the sort's intermediate buffers stay split.
+// iota (input side, pairs): each element's value is its index in the input;
+// no value array is read (a stable sort by key).
 struct KeyMap {
     int32_t um = 0, fm = 0, fl = 0;
-    bool packed = false;
+    bool packed = false, iota = false;
 };
 
 struct CorankOpts {
@@ -42,6 +44,10 @@ hipError_t launch_block_sort(int R, int NT, bool pairs, const int32_t *kin, cons
                              int32_t *kout, int32_t *vout, int64_t n, int wave_levels,
                              int lds_levels, bool blocked, hipStream_t s, int net = 0,
                              KeyMap xin = {}, KeyMap xout = {});
+
+// payload.hip: dst[i] = src[idx[i]] for 64-bit payloads
+hipError_t launch_gather_u64(const int32_t *idx, const uint64_t *src, uint64_t *dst, int64_t n,
+                             hipStream_t s);
 
 // merge.hip
 bool merge_tile_supported(int tm, bool pairs);

@@ -26,7 +26,7 @@ def _declared():
 
 def test_every_declared_symbol_is_exported():
     names = _declared()
-    assert len(names) == 27
+    assert len(names) == 29
     L = hv.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -66,6 +66,11 @@ def test_workspace_queries():
     assert w64 > L.hvms_sort_workspace_bytes(1 << 20, 1, None)
     assert L.hvms_sort64_workspace_bytes(100, None) == 0
     assert L.hvms_sort64_workspace_bytes(-1, None) == -1
+    # sort by key: indices (4 bytes per key) plus the key-value workspace
+    assert L.hvms_sort_by_key_workspace_bytes(0, None) == 0
+    assert L.hvms_sort_by_key_workspace_bytes(100, None) == 512
+    assert (L.hvms_sort_by_key_workspace_bytes(1 << 20, None)
+            == 4 * (1 << 20) + L.hvms_sort_workspace_bytes(1 << 20, 1, None))
 
 
 def test_argument_errors_before_any_launch():
@@ -102,6 +107,17 @@ def test_argument_errors_before_any_launch():
         assert f(FAKE, FAKE, 1 << 20, FAKE, 16, None, None) == -2
         assert f(FAKE, FAKE, 10, None, 0, None, ctypes.byref(bad)) == -4
         assert f(FAKE, FAKE, 10, None, 0, None, ctypes.byref(v4)) == -4       # keys-only merger
+    f = L.hvms_sort_by_key_i32_p64
+    V1, V2 = ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    assert f(FAKE, None, FAKE, V2, 5, None, 0, None, None) == -1
+    assert f(FAKE, V1, FAKE, V2, 0, None, 0, None, None) == 0
+    assert f(FAKE, V1, FAKE, V2, -1, None, 0, None, None) == -1
+    assert f(FAKE, V1, FAKE, V2, 2**31, None, 0, None, None) == -1         # int32 indices
+    assert f(FAKE, V1, FAKE, ctypes.c_void_p(0x300004), 5, None, 0, None, None) == -1
+    assert f(FAKE, V1, FAKE, V1, 5, None, 0, None, None) == -1             # payloads alias
+    assert f(FAKE, V1, FAKE, ctypes.c_void_p(0x200000 + 8 * 4), 5, None, 0, None, None) == -1
+    assert f(FAKE, V1, FAKE, V2, 5, None, 0, None, None) == -2             # needs workspace
+    assert f(FAKE, V1, FAKE, V2, 10, None, 0, None, ctypes.byref(v4)) == -4
     assert L.hvms_sort_runs_i32(FAKE, FAKE, 100, 2, None, None) == -1        # run below R
     assert L.hvms_sort_runs_i32(FAKE, FAKE, 100, 20, None, None) == -1       # run above tile
     assert L.hvms_merge_pass_i32(FAKE, FAKE, 100, 3000, None, 0, None, None) == -1  # not 2^k

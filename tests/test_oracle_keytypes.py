@@ -147,3 +147,40 @@ def test_f64_golden_finite_values_ascend(golden_dir):
     want = _golden64(golden_dir).view(np.float64)
     fin = want[np.isfinite(want)]
     assert (np.diff(fin) >= 0).all() and (np.diff(fin) == 0).sum() == 1
+
+
+# ----------------------------------------------- 64-bit payloads (stable)
+
+@pytest.mark.parametrize("n", [0, 1, 2, 13, 1000, 100003])
+def test_sort_by_key_p64_matches_numpy_stable_argsort(n):
+    rng = np.random.default_rng(400 + n)
+    k = rng.integers(-20, 20, size=n).astype(np.int32)          # many ties
+    k[: n // 7] = rng.choice(np.array([-2**31, 2**31 - 1], dtype=np.int32), size=n // 7)
+    v = rng.integers(0, 2**64, size=n, dtype=np.uint64)
+    ko, vo = oracle.sort_by_key_p64(k, v)
+    order = np.argsort(k, kind="stable")
+    assert np.array_equal(ko, k[order]) and np.array_equal(vo, v[order])
+
+
+def test_sort_by_key_p64_keeps_input_order_of_equal_keys():
+    # payload = input position: within each key the payloads must ascend
+    k = np.array([3, 1, 3, 2, 1, 3, 1], dtype=np.int32)
+    v = np.arange(7, dtype=np.int64) * 10
+    ko, vo = oracle.sort_by_key_p64(k, v)
+    assert list(ko) == [1, 1, 1, 2, 3, 3, 3]
+    assert list(vo) == [10, 40, 60, 30, 0, 20, 50]
+    assert vo.dtype == np.int64
+
+
+def test_sort_by_key_p64_brute_force_small():
+    # every arrangement of a 6-element input with ties: the result is the
+    # unique stable order
+    import itertools
+    base = [(2, 100), (0, 101), (2, 102), (1, 103), (0, 104), (2, 105)]
+    for perm in itertools.permutations(range(6)):
+        items = [base[i] for i in perm]
+        k = np.array([a for a, _ in items], dtype=np.int32)
+        v = np.array([b for _, b in items], dtype=np.uint64)
+        ko, vo = oracle.sort_by_key_p64(k, v)
+        want = sorted(items, key=lambda kv: kv[0])     # Python's sort is stable
+        assert list(ko) == [a for a, _ in want] and list(vo) == [b for _, b in want]
