@@ -359,7 +359,9 @@ __device__ __forceinline__ void serial_merge(const V &S, int alen, int boff, int
 // bit patterns (equal elements are identical, and the pad is the maximum).
 // Reads S up to VT - 1 positions past each run's end: the caller's LDS
 // array must extend that far.
-template <int VT, typename V, typename T>
+// MASK = false: the caller guarantees that the VT - 1 positions after each
+// run hold the maximum of the order (sentinels), so no read needs a mask.
+template <int VT, bool MASK = true, typename V, typename T>
 __device__ __forceinline__ void reg_merge(const V &S, int alen, int boff, int blen, int i, int j,
                                           T (&out)[VT])
 {
@@ -368,8 +370,13 @@ __device__ __forceinline__ void reg_merge(const V &S, int alen, int boff, int bl
     for (int k = 0; k < VT; ++k) {
         const T x = S[i + k];
         const T y = S[boff + j + k];
-        out[k] = i + k < alen ? x : Traits<T>::kMax;
-        b[k] = j + k < blen ? y : Traits<T>::kMax;
+        if constexpr (MASK) {
+            out[k] = i + k < alen ? x : Traits<T>::kMax;
+            b[k] = j + k < blen ? y : Traits<T>::kMax;
+        } else {
+            out[k] = x;
+            b[k] = y;
+        }
     }
 #pragma unroll
     for (int k = 0; k < VT; ++k) {

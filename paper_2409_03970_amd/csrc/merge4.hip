@@ -410,8 +410,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
             rn = gn + step < last ? load_rec(gn + step) : 0;
         }
 
-        // level 1: X = A (+) B into M[0, nx), Y = C (+) D into M[nx, cnt).
-        // Thread t produces outputs [t*VT, t*VT + VT) of that concatenation;
+        // level 1: X = A (+) B into M[0, nx), Y = C (+) D into M[nx + VT,
+        // cnt + VT), with VT sentinels (the maximum of the order) after each,
+        // so that level 2 reads past either run's end without masks.
+        // Thread t produces outputs [t*VT, t*VT + VT) of X followed by Y;
         // the one thread whose range crosses nx also writes the head of Y,
         // whose co-rank at diagonal 0 is 0 (no search).
         const int nxw = cur.nx, nyw = cur.cnt - cur.nx;
@@ -429,7 +431,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
                 T v[VT];
                 reg_merge<VT>(P, alen, boff, blen, i, diag - i, v);
                 const LdsSkew<T> MW{M, 0};
-                put_row<VT>(MW, o, v, (isx ? nxw : cur.cnt) - o);
+                put_row<VT>(MW, isx ? o : o + VT, v, (isx ? nxw : cur.cnt) - o);
                 if (isx && o + VT > nxw && nyw > 0) {
                     const LdsPlain<T> Q{S, cur.base[2]};
                     reg_merge<VT>(Q, cur.len[2], cur.base[3] - cur.base[2], cur.len[3], 0, 0, v);
@@ -437,18 +439,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
 #pragma unroll
                     for (int k = 0; k < VT; ++k)
                         if (k < lim2)
-                            MW[nxw + k] = v[k];
+                            MW[nxw + VT + k] = v[k];
                 }
+            }
+            if (t < 2 * VT) {  // sentinels at [nx, nx + VT) and [cnt + VT, cnt + 2 VT)
+                const LdsSkew<T> MW{M, 0};
+                MW[t < VT ? nxw + t : cur.cnt + t] = Traits<T>::kMax;
             }
         }
         lds_barrier();
 
-        // level 2: X (+) Y
+        // level 2: X (+) Y, reads past the runs' ends land on sentinels
         const LdsSkew<T> MX{M, 0};
         const int diag = t * VT < cur.cnt ? t * VT : cur.cnt;
-        const int i = lds_corank(MX, nxw, nxw, nyw, diag);
+        const int i = lds_corank(MX, nxw, nxw + VT, nyw, diag);
         T out[VT];
-        reg_merge<VT>(MX, nxw, nxw, nyw, i, diag - i, out);
+        reg_merge<VT, false>(MX, nxw, nxw + VT, nyw, i, diag - i, out);
         if (key_map_on(xout)) {  // wave-uniform: the last pass of a uint32 / float32 sort
 #pragma unroll
             for (int k = 0; k < VT; ++k)
@@ -471,7 +477,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
 
 bool merge4_supported(int tm, bool pairs)
 {
-    return pairs ? (tm == 2048 || tm == 4096) : (tm == 4096 || tm == 8192);
+    return pairs ? (tm == 2048 || tm == 4096) : (tm == 4096 || tm == 8192 || tm == 16384);
 }
 
 size_t merge4_record_bytes() { return sizeof(Quad); }
@@ -551,6 +557,9 @@ hipError_t launch_merge4_pass(int tm, bool pairs, const int32_t *kin, const int3
     case 8192:
         return pairs ? hipErrorInvalidValue
                      : launch_m4<512, 16, int32_t>(kin, vin, kout, vout, n, run, rec, occupancy, s, xout);
+    case 16384:
+        return pairs ? hipErrorInvalidValue
+                     : launch_m4<1024, 16, int32_t>(kin, vin, kout, vout, n, run, rec, occupancy, s, xout);
     }
     return hipErrorInvalidValue;
 }

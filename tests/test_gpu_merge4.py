@@ -93,3 +93,11 @@ def test_four_way_requested_with_unaligned_output(offset):
     ek, ev = oracle.sort_pairs(k.cpu().numpy(), v.cpu().numpy())
     assert np.array_equal(ko.cpu().numpy(), ek)
     assert np.array_equal(vbig[offset:].cpu().numpy(), ev)
+
+
+@pytest.mark.parametrize("tiles", [2, 3, 4, 5, 8, 9, 17, 33])
+def test_four_way_tile_16384(tiles):
+    # R16 x 512 threads: 8192-key block tiles, four-way merge tiles of 16384
+    n = tiles * 8192 - (777 if tiles > 2 else 0)
+    x = inputs.keys(n, "zipf", seed=40 + tiles, device=DEV)
+    _check(x, {"keys_per_lane": 16, "block_threads": 512, "merge_tile": 16384, "merge_ways": 4})
