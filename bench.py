@@ -240,18 +240,34 @@ def _median_ms(fn, reps=3):
 
 
 def _mode_stats(x, out, ws, opts, params, mode, radius=12):
-    st = torch.zeros(8, dtype=torch.int64, device=x.device)
+    """One co-rank mode on one input: sort time (median), the co-rank phase
+    of every merge pass (library events, a run without statistics), then
+    the co-rank statistics of one more run (mean and p99 probes; for the
+    predicting modes fallback rate, mean / p99 bound / max |error|)."""
+    n = x.numel()
+    st = torch.zeros(hv.STATS_WORDS, dtype=torch.int64, device=x.device)
     o = dict(opts, corank_mode=mode, radius_log2=radius, cdf_params=params)
     ms = _median_ms(lambda: hv.hvms_sort_i32(x, out, ws, opts=o))
+    R = opts.get("keys_per_lane") or 16
+    NT = opts.get("block_threads") or 512
+    passes = merge_passes(n, R * NT, opts.get("merge_ways") or 2)
+    ev = make_events(2 + 2 * passes)
+    hv.hvms_sort_i32(x, out, ws, opts=dict(o, events=ev))
+    torch.cuda.synchronize()
+    cr_ms = [ev[1 + 2 * p].elapsed_time(ev[2 + 2 * p]) for p in range(passes)]
     o["stats"] = st
     hv.hvms_sort_i32(x, out, ws, opts=o)
     torch.cuda.synchronize()
     c = st.cpu().tolist()
-    r = {"ms": round(ms, 3), "gkeys_per_s": round(x.numel() / ms / 1e6, 3),
-         "probes_per_corank": round(c[1] / max(c[0], 1), 2)}
+    s = hv.corank_stats(c)
+    r = {"ms": round(ms, 3), "gkeys_per_s": round(n / ms / 1e6, 3),
+         "probes_per_corank": s["probes_mean"], "probes_p99": s["probes_p99"],
+         "corank_ms_per_pass": [round(t, 4) for t in cr_ms],
+         "corank_ms_total": round(sum(cr_ms), 3)}
     if mode != hv.CORANK_BINARY:
-        r.update(fallback_rate=round(c[2] / max(c[0], 1), 4),
-                 mean_abs_err=round(c[3] / max(c[0], 1), 1), max_err=int(c[4]))
+        r.update(fallback_rate=s.get("fallback_rate"), mean_abs_err=s.get("abs_err_mean"),
+                 abs_err_p99_at_most=s.get("abs_err_p99_at_most"), max_err=s.get("max_err"),
+                 predicted_coranks=s.get("predicted", 0))
     return r
 
 
@@ -430,7 +446,7 @@ def config5_bench():
     dists = inputs.segment_distributions(nseg, seed=0)
     offs = inputs.offsets_from_sizes(sizes).tolist()
     t = {"learned": 0.0, "binary": 0.0, "per_segment": 0.0, "train": 0.0}
-    stats = torch.zeros(8, dtype=torch.int64, device=dev)
+    stats = torch.zeros(hv.STATS_WORDS, dtype=torch.int64, device=dev)
     total, ok = 0, True
     L = hv.lib()
     for s0, s1, _ in hv.segment_groups(offs, 1 << 31):
@@ -502,8 +518,7 @@ def config5_bench():
             "per_segment_plain_ms": round(t["per_segment"], 1),
             "per_segment_gpairs_per_s": round(total / t["per_segment"] / 1e6, 2),
             "training_ms_all_groups": round(t["train"], 1),
-            "learned_probes_per_corank": round(c[1] / max(c[0], 1), 2),
-            "learned_fallback_rate": round(c[2] / max(c[0], 1), 4)}
+            "learned_corank": hv.corank_stats(c)}
 
 
 def table2_bench():
@@ -616,11 +631,25 @@ def main():
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--merge-tile", type=int, default=0)
     ap.add_argument("--wave-levels", type=int, default=0, help="levels + 1; 0 = default")
+    ap.add_argument("--only", choices=("learned_2p30_mixture",),
+                    help="diagnostic: run just this measurement (no headline) and print "
+                         "its record; used by the co-rank counter profiles")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the sort is a single-GPU library)", file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        dev = torch.device("cuda", 0)
+        torch.cuda.set_device(dev)
+        if args.profile_copy:  # a plain 1 GiB copy of known size (counter calibration)
+            a = torch.zeros(1 << 28, dtype=torch.int32, device=dev)
+            torch.empty_like(a).copy_(a)
+            torch.cuda.synchronize()
+            del a
+        rec = {"only": args.only, **learned_bench()}
+        print(json.dumps(rec), flush=True)
+        return
 
     log2n, dists = WORKLOADS[args.workload]
     n = 1 << log2n

@@ -110,7 +110,16 @@ enum {
     HVMS_STAT_FALLBACKS = 2, /* bounded searches that fell back to binary    */
     HVMS_STAT_ABS_ERR = 3,   /* sum of |prediction - co-rank|                */
     HVMS_STAT_MAX_ERR = 4,   /* max |prediction - co-rank|                   */
-    HVMS_STATS_WORDS = 8
+    HVMS_STAT_PREDICTED = 5, /* co-ranks that used a prediction (learned or
+                              * linear mode and more than 3 candidates);
+                              * words 2-4 and the error histogram count these */
+    /* 64 words: co-ranks by probe pairs read, bin p = p probes (63 = 63 or
+     * more); every co-rank of every mode lands in one bin */
+    HVMS_STAT_PROBE_HIST = 8,
+    /* 64 words: predicted co-ranks by the bit length of
+     * |prediction - co-rank|: bin 0 exact, bin b an error in [2^(b-1), 2^b) */
+    HVMS_STAT_ERR_HIST = 72,
+    HVMS_STATS_WORDS = 136
 };
 
 const char *hvms_status_string(int status);

@@ -14,7 +14,7 @@ import torch
 
 __all__ = [
     "HvmsError", "Options", "lib", "CORANK_BINARY", "CORANK_LEARNED", "CORANK_LINEAR",
-    "CDF_PARAMS", "STAT_NAMES",
+    "CDF_PARAMS", "STAT_NAMES", "STATS_WORDS", "corank_stats",
     "hvms_sort_i32", "hvms_sort_pairs_i32", "hvms_sort_runs_i32", "hvms_merge_pass_i32",
     "hvms_corank_i32", "hvms_segmented_sort_i32", "hvms_segmented_sort_pairs_i32",
     "hvms_cdf_forward", "hvms_cdf_backward", "hvms_cdf_adam_step", "hvms_cdf_train",
@@ -31,7 +31,43 @@ LIB_PATH = os.path.join(_HERE, "libhvms.so")
 
 CORANK_BINARY, CORANK_LEARNED, CORANK_LINEAR = 0, 1, 2
 CDF_PARAMS = 1153
-STAT_NAMES = ("coranks", "probes", "fallbacks", "abs_err_sum", "max_err")
+STAT_NAMES = ("coranks", "probes", "fallbacks", "abs_err_sum", "max_err", "predicted")
+STATS_WORDS = 136        # words 8..71: probe histogram; 72..135: |error| bit-length histogram
+
+
+def _quantile_bin(hist, q):
+    """Smallest bin b with at least a fraction q of the histogram's mass in
+    bins 0..b (None for an empty histogram)."""
+    total = sum(hist)
+    if total == 0:
+        return None
+    need, acc = q * total, 0
+    for b, h in enumerate(hist):
+        acc += h
+        if acc >= need:
+            return b
+    return len(hist) - 1
+
+
+def corank_stats(words):
+    """Summary of a co-rank stats buffer (HVMS_STATS_WORDS uint64 words, as
+    a list or tensor): counts, mean and 99th-percentile probes per co-rank,
+    and over the co-ranks that used a prediction (learned / linear mode) the
+    fallback rate, mean, 99th-percentile bound and max of
+    |prediction - co-rank|.  The error percentile comes
+    from the bit-length histogram, so it is reported as an upper bound
+    (2^b - 1 for bin b)."""
+    w = [int(v) for v in (words.tolist() if hasattr(words, "tolist") else words)]
+    n = max(w[0], 1)
+    ph, eh = w[8:72], w[72:136]
+    r = {"coranks": w[0], "probes_mean": round(w[1] / n, 2),
+         "probes_p99": _quantile_bin(ph, 0.99)}
+    if w[5]:
+        p = w[5]
+        b = _quantile_bin(eh, 0.99)
+        r.update(predicted=p, fallback_rate=round(w[2] / p, 4), abs_err_mean=round(w[3] / p, 1),
+                 abs_err_p99_at_most=(1 << b) - 1, max_err=w[4])
+    return r
 
 
 class HvmsError(RuntimeError):
@@ -150,6 +186,15 @@ def _opts(opts):
     o = Options()
     for k, v in opts.items():
         if k in ("cdf_params", "stats"):
+            if k == "stats" and v is not None and (
+                    v.element_size() != 8 or v.numel() < STATS_WORDS or not v.is_contiguous()):
+                # the co-rank kernels write all STATS_WORDS words
+                raise ValueError(f"stats must be a contiguous 64-bit tensor of at least "
+                                 f"{STATS_WORDS} words")
+            if k == "cdf_params" and v is not None and (
+                    v.dtype != torch.float32 or v.numel() < CDF_PARAMS or not v.is_contiguous()):
+                raise ValueError(f"cdf_params must be a contiguous float32 tensor of "
+                                 f"{CDF_PARAMS} values")
             setattr(o, k, None if v is None else v.data_ptr())
         elif k == "events":
             # torch.cuda.Event objects (already recorded once, so they exist)

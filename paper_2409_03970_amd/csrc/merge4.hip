@@ -250,6 +250,7 @@ __global__ __launch_bounds__(256) void quad_corank_kernel(const int32_t *__restr
     if (stats) {
         atomicAdd(stats + 0, 1ull);
         atomicAdd(stats + 1, (unsigned long long)probes);
+        atomicAdd(stats + 8 + (probes < 63 ? probes : 63), 1ull);
     }
 }
 

@@ -114,7 +114,8 @@ __device__ int64_t find_corank(const CorankCtl &c, FA A, FB B, KA Akey, KB Bkey,
     const int64_t hi = d < m ? d : m;
     unsigned probes = 0, fallback = 0;
     int64_t res, pred = 0;
-    if (c.mode == 0 || hi - lo <= 2) {
+    const bool predicted = c.mode != 0 && hi - lo > 2;
+    if (!predicted) {
         res = binary_corank<T>(A, B, d, lo, hi, probes);
     } else {
         pred = predict_corank(c, Akey, Bkey, m, k, d, pre);
@@ -139,10 +140,14 @@ __device__ int64_t find_corank(const CorankCtl &c, FA A, FB B, KA Akey, KB Bkey,
             (unsigned long long)(res > pred ? res - pred : pred - res);
         atomicAdd(c.stats + 0, 1ull);
         atomicAdd(c.stats + 1, (unsigned long long)probes);
-        if (c.mode != 0) {
+        atomicAdd(c.stats + 8 + (probes < 63 ? probes : 63), 1ull);
+        if (predicted) {
+            atomicAdd(c.stats + 5, 1ull);
             atomicAdd(c.stats + 2, (unsigned long long)fallback);
             atomicAdd(c.stats + 3, err);
             atomicMax(c.stats + 4, err);
+            const int bits = err ? 64 - __clzll((long long)err) : 0;
+            atomicAdd(c.stats + 72 + (bits < 63 ? bits : 63), 1ull);
         }
     }
     return res;

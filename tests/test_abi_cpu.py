@@ -168,3 +168,32 @@ def test_cdf_argument_errors():
     assert L.hvms_cdf_train(FAKE, FAKE, FAKE, FAKE, 0, 10, 1, 1e-3, 0, FAKE, 1 << 30, None) == -1
     assert L.hvms_cdf_sample_i32(FAKE, 0, 5, 1, FAKE, None) == -1
     assert L.hvms_cdf_sample_i32(FAKE, 10, 0, 1, FAKE, None) == 0
+
+
+def test_stats_and_model_buffers_are_checked_before_any_call():
+    import torch
+    for bad in (torch.zeros(8, dtype=torch.int64), torch.zeros(136, dtype=torch.int32)):
+        with pytest.raises(ValueError):
+            hv._opts({"stats": bad})
+    hv._opts({"stats": torch.zeros(hv.STATS_WORDS, dtype=torch.int64)})
+    with pytest.raises(ValueError):
+        hv._opts({"cdf_params": torch.zeros(100, dtype=torch.float32)})
+    # the header's stats layout and the binding agree
+    text = open(HEADER).read()
+    assert re.search(r"HVMS_STATS_WORDS\s*=\s*%d" % hv.STATS_WORDS, text)
+    assert re.search(r"HVMS_STAT_PROBE_HIST\s*=\s*8\b", text)
+    assert re.search(r"HVMS_STAT_ERR_HIST\s*=\s*72\b", text)
+
+
+def test_corank_stats_summary_percentiles():
+    w = [0] * hv.STATS_WORDS
+    w[0], w[1] = 100, 1000
+    w[8 + 9], w[8 + 10], w[8 + 20] = 90, 9, 1          # probes: p99 -> 10
+    w[2], w[3], w[4], w[5] = 5, 700, 300, 100
+    w[72 + 0], w[72 + 3], w[72 + 9] = 50, 49, 1         # |err| bit lengths
+    r = hv.corank_stats(w)
+    assert r["probes_mean"] == 10.0 and r["probes_p99"] == 10
+    assert r["abs_err_p99_at_most"] == 7 and r["max_err"] == 300
+    assert r["fallback_rate"] == 0.05 and r["abs_err_mean"] == 7.0
+    w[8 + 20] = 5                                       # 5 % at 20 probes: p99 -> 20
+    assert hv.corank_stats(w)["probes_p99"] == 20

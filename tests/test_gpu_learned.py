@@ -153,7 +153,7 @@ def test_learned_sort_is_exact(dist):
     params = hv.fit_cdf_model(x, frac=0.01, steps=200, batch=8192, lr=3e-3, seed=8)
     want = oracle.sort(x.cpu().numpy())
     for mode in (hv.CORANK_LEARNED, hv.CORANK_LINEAR):
-        st = torch.zeros(8, dtype=torch.int64, device=DEV)
+        st = torch.zeros(hv.STATS_WORDS, dtype=torch.int64, device=DEV)
         y = hv.sort(x, opts={"corank_mode": mode, "cdf_params": params, "radius_log2": 10,
                              "stats": st})
         assert np.array_equal(y.cpu().numpy(), want), mode
@@ -169,7 +169,7 @@ def test_learned_prediction_exact_on_disjoint_runs():
     params = hv.fit_cdf_model(x, frac=0.01, steps=300, batch=8192, lr=3e-3, seed=9)
     res = {}
     for mode in (hv.CORANK_LEARNED, hv.CORANK_LINEAR, hv.CORANK_BINARY):
-        st = torch.zeros(8, dtype=torch.int64, device=DEV)
+        st = torch.zeros(hv.STATS_WORDS, dtype=torch.int64, device=DEV)
         y = hv.sort(x, opts={"corank_mode": mode, "cdf_params": params, "radius_log2": 8,
                              "stats": st})
         assert torch.equal(y, x)
@@ -177,6 +177,46 @@ def test_learned_prediction_exact_on_disjoint_runs():
     learned, linear, binary = res[hv.CORANK_LEARNED], res[hv.CORANK_LINEAR], res[hv.CORANK_BINARY]
     assert learned[2] < linear[2]                   # fewer fallbacks
     assert learned[1] < binary[1]                   # fewer probes than binary search
+    # the error statistics cover the predicted co-ranks only: on disjoint
+    # runs every prediction is exact
+    assert learned[5] > 0 and learned[4] == 0 and learned[3] == 0
+    assert sum(learned[72:136]) == learned[5] == learned[72]
+
+
+def _check_histograms(w, mode):
+    n = w[0]
+    ph, eh = w[8:72], w[72:136]
+    assert sum(ph) == n                                         # every co-rank in one bin
+    if ph[63] == 0:
+        assert sum(p * h for p, h in enumerate(ph)) == w[1]      # exact probe total
+    if mode == hv.CORANK_BINARY:
+        assert w[5] == 0 and sum(eh) == 0 and w[2] == w[3] == w[4] == 0
+        return
+    assert 0 < w[5] <= n and sum(eh) == w[5] and w[2] <= w[5]
+    top = max(b for b, h in enumerate(eh) if h)                 # highest error bin
+    assert top == int(w[4]).bit_length()
+    lo = sum(h << (b - 1) for b, h in enumerate(eh) if b)        # error sum bounds
+    hi = sum(h * ((1 << b) - 1) for b, h in enumerate(eh))
+    assert lo <= w[3] <= hi
+
+
+@pytest.mark.parametrize("dist", ["uniform", "mixture", "distinct16"])
+@pytest.mark.parametrize("ways", [2, 4])
+def test_corank_histograms_are_consistent(dist, ways):
+    n = 2_000_003
+    x = inputs.keys(n, dist, seed=12, device=DEV)
+    params = hv.fit_cdf_model(x, frac=0.01, steps=150, batch=8192, lr=3e-3, seed=12)
+    want = oracle.sort(x.cpu().numpy())
+    for mode in (hv.CORANK_BINARY, hv.CORANK_LEARNED, hv.CORANK_LINEAR):
+        st = torch.zeros(hv.STATS_WORDS, dtype=torch.int64, device=DEV)
+        y = hv.sort(x, opts={"corank_mode": mode, "cdf_params": params, "radius_log2": 9,
+                             "stats": st, "merge_ways": ways})
+        assert np.array_equal(y.cpu().numpy(), want)
+        w = st.cpu().tolist()
+        assert w[0] > 0
+        _check_histograms(w, mode)
+        s = hv.corank_stats(w)
+        assert s["probes_p99"] is not None and s["probes_p99"] * 1.0 >= 0
 
 
 def test_corank_list_learned_matches_oracle():

@@ -257,7 +257,7 @@ def test_corank_stats_count_probes():
     A = torch.arange(0, 2000000, 2, device=DEV, dtype=torch.int32)
     B = torch.arange(1, 2000000, 2, device=DEV, dtype=torch.int32)
     diag = torch.arange(1, 2000000, 1001, device=DEV, dtype=torch.int64)
-    st = torch.zeros(8, dtype=torch.int64, device=DEV)
+    st = torch.zeros(hv.STATS_WORDS, dtype=torch.int64, device=DEV)
     got = hv.corank(A, B, diag, opts={"corank_mode": hv.CORANK_LINEAR, "radius_log2": 4, "stats": st})
     assert torch.equal(got, (diag + 1) // 2)
     s = st.cpu().tolist()
