@@ -234,3 +234,22 @@ def test_full_size_50k_segments_learned_pairs():
         torch.cuda.empty_cache()
     assert total == offs[-1] and checked > 0
     _say("pairs", total, "oracle-checked segments", checked)
+
+
+def test_all_permutations_of_8_as_segments():
+    # all 8! = 40,320 arrangements of 0..7 as segments of one call: every
+    # segment must come back as 0..7; the pair form keeps each key's position
+    import itertools
+    perms = np.array(list(itertools.permutations(range(8))), dtype=np.int32)
+    k = torch.from_numpy(perms.reshape(-1).copy()).to(DEV)
+    offs = torch.arange(0, perms.size + 1, 8, dtype=torch.int64)
+    _say("segmented all 8! permutations")
+    y = hv.segmented_sort(k, offs).cpu().numpy().reshape(-1, 8)
+    assert (y == np.arange(8, dtype=np.int32)).all()
+    pos = np.tile(np.arange(8, dtype=np.int32), len(perms))
+    v = torch.from_numpy(pos).to(DEV)
+    ko, vo = hv.segmented_sort_pairs(k, v, offs)
+    ko, vo = ko.cpu().numpy().reshape(-1, 8), vo.cpu().numpy().reshape(-1, 8)
+    assert (ko == np.arange(8)).all()
+    # value j of segment s is where key j stood: perms[s, vo[s, j]] == j
+    assert (np.take_along_axis(perms, vo, axis=1) == np.arange(8)).all()

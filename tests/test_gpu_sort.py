@@ -322,3 +322,19 @@ def test_alternative_column_networks_full_sort(net, NT):
     x = inputs.keys(n, "gaussian", seed=net, device=DEV)
     y = hv.sort(x, opts={"keys_per_lane": 16, "block_threads": NT, "column_network": net})
     assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy()))
+
+
+def test_sort_every_size_up_to_130():
+    for n in range(1, 131):
+        x = inputs.keys(n, "uniform", seed=1000 + n, device=DEV)
+        y = hv.sort(x)
+        assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy())), n
+
+
+@pytest.mark.parametrize("k", range(1, 25))
+def test_sort_powers_of_two_and_neighbours(k):
+    for n in ((1 << k) - 1, 1 << k, (1 << k) + 1):
+        _say("sort n =", n)
+        x = inputs.keys(n, "zipf", seed=k, device=DEV)
+        y = hv.sort(x)
+        assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy())), n
