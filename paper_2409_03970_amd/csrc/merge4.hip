@@ -233,7 +233,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void quad_corank_kernel(const int32_t *__restrict__ kin,
                                                           const int32_t *__restrict__ vin,
                                                           int64_t n, int64_t run, int64_t tm,
-                                                          int64_t ntiles,
+                                                          int64_t ntiles, int lg4run,
                                                           const int64_t *__restrict__ grid,
                                                           Quad *__restrict__ out,
                                                           unsigned long long *stats)
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(256) void quad_corank_kernel(const int32_t *__restr
     if (g >= ntiles)
         return;
     const int64_t o0 = g * tm;
-    const int64_t gq = o0 / (4 * run);
+    const int64_t gq = o0 >> lg4run;
     const Group<T> G = group_of<T>(kin, vin, n, run, gq);
     const int64_t d = o0 - G.gb;
     unsigned probes = 0;
@@ -310,6 +310,54 @@ __device__ __forceinline__ Tile4 tile4_geo(const Group<T> &G, int64_t run, int64
     return t;
 }
 
+// A tile whose outputs all come from one window (runs with disjoint key
+// ranges, as in presorted input) is that window in order: copy it out of S,
+// where it starts at index off, to the tile's outputs (abs0 a multiple of 4),
+// applying the last pass's key map.  Every read index is below off + cnt + 3
+// (off <= 3, cnt <= TM), inside S.
+template <int NT, int CH, typename T, bool PK>
+__device__ __forceinline__ void copy_window(const T *S, int off, int32_t *__restrict__ k,
+                                            int32_t *__restrict__ v, int64_t abs0, int cnt,
+                                            int t, KeyMap xout)
+{
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+        const int c = t + NT * q;
+        if (4 * c >= cnt)
+            continue;
+        const int64_t e = abs0 + 4 * c;
+        T x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            x[u] = S[off + 4 * c + u];
+        if (key_map_on(xout)) {  // wave-uniform: the last pass of a mapped sort
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                x[u] = map_elem(x[u], xout);
+        }
+        if (4 * c + 4 <= cnt) {
+            if constexpr (sizeof(T) == 4) {
+                *(int4 *)(k + e) = make_int4(x[0], x[1], x[2], x[3]);
+            } else if constexpr (PK) {
+                typedef int64_t V2 __attribute__((ext_vector_type(2)));
+                V2 *o = (V2 *)((int64_t *)k + e);
+                o[0] = V2{x[0], x[1]};
+                o[1] = V2{x[2], x[3]};
+            } else {
+                *(int4 *)(k + e) =
+                    make_int4(pair_key(x[0]), pair_key(x[1]), pair_key(x[2]), pair_key(x[3]));
+                *(int4 *)(v + e) =
+                    make_int4(pair_val(x[0]), pair_val(x[1]), pair_val(x[2]), pair_val(x[3]));
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (4 * c + u < cnt)
+                    store_elem<T, PK>(k, v, e + u, x[u]);
+        }
+    }
+}
+
 // PK: the output is one packed 64-bit array at kout (the last pass of a
 // 64-bit key sort).
 template <int NT, int VT, typename T, bool PK = false>
@@ -318,7 +366,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
                                                          int32_t *__restrict__ kout,
                                                          int32_t *__restrict__ vout, int64_t n,
                                                          int64_t run, const Quad *__restrict__ rec,
-                                                         int64_t ntiles, KeyMap xout)
+                                                         int64_t ntiles, int lg4run, KeyMap xout)
 {
     constexpr int TM = NT * VT;
     constexpr int CH = VT / 4 + 1;  // chunk slots per thread: TM/4 + 6 chunks at most
@@ -353,7 +401,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
         q1.x = rd(rv, 3);
         q1.a = rd(rv, 4);
         q1.c = rd(rv, 5);
-        const Group<T> G = group_of<T>(kin, vin, n, run, (g * TM) / (4 * run));
+        // runs and tiles are powers of two: the group index is a shift
+        const Group<T> G = group_of<T>(kin, vin, n, run, (g * TM) >> lg4run);
         return tile4_geo<T>(G, run, TM, g, q0, q1);
     };
 
@@ -409,6 +458,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
             nxt = geo_of(gn, rn);
             prefetch(nxt);
             rn = gn + step < last ? load_rec(gn + step) : 0;
+        }
+
+        // a tile fed by one window only: no merging (tile-uniform branch)
+        // (constant indices only: a runtime index would put cur in scratch)
+        const int src = cur.len[0] == cur.cnt   ? cur.base[0]
+                        : cur.len[1] == cur.cnt ? cur.base[1]
+                        : cur.len[2] == cur.cnt ? cur.base[2]
+                        : cur.len[3] == cur.cnt ? cur.base[3]
+                                                : -1;
+        if (src >= 0) {
+            copy_window<NT, CH, T, PK>(S, src, kout, vout, cur.gb + cur.o0, cur.cnt, t, xout);
+            lds_barrier();  // the next tile's chunks overwrite S
+            if (!more)
+                break;
+            g = gn;
+            cur = nxt;
+            continue;
         }
 
         // level 1: X = A (+) B into M[0, nx), Y = C (+) D into M[nx + VT,
@@ -476,6 +542,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
 
 }  // namespace
 
+// log2 of a power of two
+static int ilog2_pow2(int64_t x)
+{
+    int l = 0;
+    while (((int64_t)1 << l) < x)
+        ++l;
+    return l;
+}
+
 bool merge4_supported(int tm, bool pairs)
 {
     return pairs ? (tm == 2048 || tm == 4096) : (tm == 4096 || tm == 8192 || tm == 16384);
@@ -490,7 +565,8 @@ static hipError_t launch_quad_corank(const int32_t *kin, const int32_t *vin, int
 {
     const int64_t ntiles = (n + tm - 1) / tm;
     hipLaunchKernelGGL(quad_corank_kernel<T>, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0,
-                       s, kin, vin, n, run, tm, ntiles, grid, (Quad *)rec, o.stats);
+                       s, kin, vin, n, run, tm, ntiles, ilog2_pow2(4 * run), grid, (Quad *)rec,
+                       o.stats);
     return hipGetLastError();
 }
 
@@ -510,7 +586,8 @@ static hipError_t launch_m4_1(const int32_t *kin, const int32_t *vin, int32_t *k
     if (grid > ntiles)
         grid = ntiles;
     hipLaunchKernelGGL((merge4_pipe_kernel<NT, VT, T, PK>), dim3((unsigned)grid), dim3(NT), 0, s,
-                       kin, vin, kout, vout, n, run, (const Quad *)rec, ntiles, xout);
+                       kin, vin, kout, vout, n, run, (const Quad *)rec, ntiles, ilog2_pow2(4 * run),
+                       xout);
     return hipGetLastError();
 }
 
@@ -535,7 +612,8 @@ hipError_t launch_merge4_corank(int tm, bool pairs, const int32_t *kin, const in
 {
     // the sample grid: two-way co-ranks of every tile-aligned diagonal of the
     // pairs (A, B) and (C, D) of each group (2*run is a multiple of tm)
-    if (!merge4_supported(tm, pairs) || run <= 0 || (2 * run) % tm != 0)
+    // runs are powers of two (the kernels find a tile's group by a shift)
+    if (!merge4_supported(tm, pairs) || run <= 0 || (run & (run - 1)) != 0 || (2 * run) % tm != 0)
         return hipErrorInvalidValue;
     hipError_t e = launch_pass_corank(pairs, kin, vin, n, run, tm, grid, o, s);
     if (e != hipSuccess)
@@ -548,6 +626,8 @@ hipError_t launch_merge4_pass(int tm, bool pairs, const int32_t *kin, const int3
                               int32_t *kout, int32_t *vout, int64_t n, int64_t run,
                               const void *rec, int occupancy, hipStream_t s, KeyMap xout)
 {
+    if (run <= 0 || (run & (run - 1)) != 0 || (2 * run) % tm != 0)
+        return hipErrorInvalidValue;
     switch (tm) {
     case 2048:
         return pairs ? launch_m4<256, 8, int64_t>(kin, vin, kout, vout, n, run, rec, occupancy, s, xout)

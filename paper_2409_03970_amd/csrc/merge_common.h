@@ -369,6 +369,8 @@ template <typename T> __device__ __forceinline__ void put_chunk(T *S, int c, con
 // 16-byte aligned.
 // Coalesced copy of the first cnt elements of a skewed LDS array to global
 // index abs0 (a multiple of 4): thread t moves 16-byte chunks t, t + NT, ...
+// The ragged last chunk is read like the others (its 4 slots exist in W) and
+// only its stores are guarded, so it needs no addresses of its own.
 template <int NT, int CH, typename T, bool PK = false>
 __device__ __forceinline__ void copy_out(const LdsSkew<T> &W, int32_t *__restrict__ k,
                                          int32_t *__restrict__ v, int64_t abs0, int cnt, int t)
@@ -381,24 +383,24 @@ __device__ __forceinline__ void copy_out(const LdsSkew<T> &W, int32_t *__restric
         if (4 * c >= cnt)
             continue;
         const int64_t e = abs0 + 4 * c;
+        // W[4c] is 16-byte aligned in the skewed layout
+        T x[4];
+#pragma unroll
+        for (int h = 0; h < 4; h += E) {
+            const Vec y = *(const Vec *)&W[4 * c + h];
+#pragma unroll
+            for (int u = 0; u < E; ++u)
+                x[h + u] = y[u];
+        }
         if (4 * c + 4 <= cnt) {
             if constexpr (sizeof(T) == 4) {
-                // one 16-byte copy (W[4c] is 16-byte aligned in the skewed layout)
-                *(int4 *)(k + e) = *(const int4 *)&W[4 * c];
+                *(int4 *)(k + e) = make_int4(x[0], x[1], x[2], x[3]);
             } else if constexpr (PK) {
                 typedef int64_t V2 __attribute__((ext_vector_type(2)));
                 V2 *o = (V2 *)((int64_t *)k + e);
-                o[0] = *(const V2 *)&W[4 * c];
-                o[1] = *(const V2 *)&W[4 * c + 2];
+                o[0] = V2{x[0], x[1]};
+                o[1] = V2{x[2], x[3]};
             } else {
-                T x[4];
-#pragma unroll
-                for (int h = 0; h < 4; h += E) {
-                    const Vec y = *(const Vec *)&W[4 * c + h];
-#pragma unroll
-                    for (int u = 0; u < E; ++u)
-                        x[h + u] = y[u];
-                }
                 *(int4 *)(k + e) =
                     make_int4(pair_key(x[0]), pair_key(x[1]), pair_key(x[2]), pair_key(x[3]));
                 *(int4 *)(v + e) =
@@ -408,7 +410,7 @@ __device__ __forceinline__ void copy_out(const LdsSkew<T> &W, int32_t *__restric
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (4 * c + u < cnt)
-                    store_elem<T, PK>(k, v, e + u, W[4 * c + u]);
+                    store_elem<T, PK>(k, v, e + u, x[u]);
         }
     }
 }
