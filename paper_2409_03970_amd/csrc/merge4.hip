@@ -310,54 +310,6 @@ __device__ __forceinline__ Tile4 tile4_geo(const Group<T> &G, int64_t run, int64
     return t;
 }
 
-// A tile whose outputs all come from one window (runs with disjoint key
-// ranges, as in presorted input) is that window in order: copy it out of S,
-// where it starts at index off, to the tile's outputs (abs0 a multiple of 4),
-// applying the last pass's key map.  Every read index is below off + cnt + 3
-// (off <= 3, cnt <= TM), inside S.
-template <int NT, int CH, typename T, bool PK>
-__device__ __forceinline__ void copy_window(const T *S, int off, int32_t *__restrict__ k,
-                                            int32_t *__restrict__ v, int64_t abs0, int cnt,
-                                            int t, KeyMap xout)
-{
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-        const int c = t + NT * q;
-        if (4 * c >= cnt)
-            continue;
-        const int64_t e = abs0 + 4 * c;
-        T x[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            x[u] = S[off + 4 * c + u];
-        if (key_map_on(xout)) {  // wave-uniform: the last pass of a mapped sort
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                x[u] = map_elem(x[u], xout);
-        }
-        if (4 * c + 4 <= cnt) {
-            if constexpr (sizeof(T) == 4) {
-                *(int4 *)(k + e) = make_int4(x[0], x[1], x[2], x[3]);
-            } else if constexpr (PK) {
-                typedef int64_t V2 __attribute__((ext_vector_type(2)));
-                V2 *o = (V2 *)((int64_t *)k + e);
-                o[0] = V2{x[0], x[1]};
-                o[1] = V2{x[2], x[3]};
-            } else {
-                *(int4 *)(k + e) =
-                    make_int4(pair_key(x[0]), pair_key(x[1]), pair_key(x[2]), pair_key(x[3]));
-                *(int4 *)(v + e) =
-                    make_int4(pair_val(x[0]), pair_val(x[1]), pair_val(x[2]), pair_val(x[3]));
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (4 * c + u < cnt)
-                    store_elem<T, PK>(k, v, e + u, x[u]);
-        }
-    }
-}
-
 // PK: the output is one packed 64-bit array at kout (the last pass of a
 // 64-bit key sort).
 template <int NT, int VT, typename T, bool PK = false>
@@ -468,7 +420,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
                         : cur.len[3] == cur.cnt ? cur.base[3]
                                                 : -1;
         if (src >= 0) {
-            copy_window<NT, CH, T, PK>(S, src, kout, vout, cur.gb + cur.o0, cur.cnt, t, xout);
+            copy_run<NT, CH, T, PK>(LdsPlain<T>{S, 0}, src, 0, kout, vout, cur.gb + cur.o0,
+                                    cur.cnt, t, xout);
             lds_barrier();  // the next tile's chunks overwrite S
             if (!more)
                 break;

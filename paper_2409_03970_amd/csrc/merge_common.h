@@ -415,6 +415,57 @@ __device__ __forceinline__ void copy_out(const LdsSkew<T> &W, int32_t *__restric
     }
 }
 
+// A tile whose outputs all come from one window (runs with disjoint key
+// ranges, as in presorted input) is that window in order: copy it from
+// position src of the staged windows.  Output x (0 <= x < cnt) goes to
+// absolute index abs0 + shift + x, abs0 a multiple of 4; thread t moves
+// 16-byte output chunks t, t + NT, ... and the ragged chunks at both ends
+// element by element.  Applies the last pass's key map.  Reads stay inside
+// the window: Z[src .. src + cnt).
+template <int NT, int CH, typename T, bool PK, typename View>
+__device__ __forceinline__ void copy_run(const View &Z, int src, int shift,
+                                         int32_t *__restrict__ k, int32_t *__restrict__ v,
+                                         int64_t abs0, int cnt, int t, KeyMap xout)
+{
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+        const int c = t + NT * q;
+        const int x0 = 4 * c - shift;  // output index of the chunk's first slot
+        if (x0 >= cnt)
+            continue;
+        const int64_t e = abs0 + 4 * c;
+        if (x0 >= 0 && x0 + 4 <= cnt) {
+            T x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                x[u] = Z[src + x0 + u];
+            if (key_map_on(xout)) {  // wave-uniform: the last pass of a mapped sort
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    x[u] = map_elem(x[u], xout);
+            }
+            if constexpr (sizeof(T) == 4) {
+                *(int4 *)(k + e) = make_int4(x[0], x[1], x[2], x[3]);
+            } else if constexpr (PK) {
+                typedef int64_t V2 __attribute__((ext_vector_type(2)));
+                V2 *o = (V2 *)((int64_t *)k + e);
+                o[0] = V2{x[0], x[1]};
+                o[1] = V2{x[2], x[3]};
+            } else {
+                *(int4 *)(k + e) =
+                    make_int4(pair_key(x[0]), pair_key(x[1]), pair_key(x[2]), pair_key(x[3]));
+                *(int4 *)(v + e) =
+                    make_int4(pair_val(x[0]), pair_val(x[1]), pair_val(x[2]), pair_val(x[3]));
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (x0 + u >= 0 && x0 + u < cnt)
+                    store_elem<T, PK>(k, v, e + u, map_elem(Z[src + x0 + u], xout));
+        }
+    }
+}
+
 // Register targets of the merge kernels: waves per SIMD that they fit
 // without spilling (keys 4, or 2 at VT = 32; pairs 3).  A register over an
 // allocation step costs a whole wave, so the target is stated, not left to
