@@ -467,11 +467,14 @@ def config5_bench():
             return {"corank_mode": hv.CORANK_LEARNED, "cdf_params": p, "stats": stats}
 
         res = {}
+        # the group workspace is allocated before the timed calls
+        gws = hv._workspace(hv.grouped_workspace_bytes(offs_local, 1 << 30), dev)
         for mode in ("learned", "binary"):
             k, v = k0.clone(), v0.clone()
             torch.cuda.synchronize()
             if mode == "learned":
-                hv.segmented_sort_pairs_grouped(k, v, offs_local, 1 << 30, opts_for_group=learned)
+                hv.segmented_sort_pairs_grouped(k, v, offs_local, 1 << 30, opts_for_group=learned,
+                                                ws=gws)
                 k, v = k0.clone(), v0.clone()      # first run trained the models
                 fn = (lambda kg, gi: {"corank_mode": hv.CORANK_LEARNED, "cdf_params": params[gi]})
             else:
@@ -479,14 +482,15 @@ def config5_bench():
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
-            hv.segmented_sort_pairs_grouped(k, v, offs_local, 1 << 30, opts_for_group=fn)
+            hv.segmented_sort_pairs_grouped(k, v, offs_local, 1 << 30, opts_for_group=fn,
+                                            ws=gws)
             b.record()
             torch.cuda.synchronize()
             t[mode] += a.elapsed_time(b)
             res[mode] = (k, v)
         ok &= bool(torch.equal(res["learned"][0], res["binary"][0]))
         ok &= bool(torch.equal(res["learned"][1], res["binary"][1]))
-        del res
+        del res, gws
         # one plain pair sort per segment, same inputs
         k, v = k0.clone(), v0.clone()
         maxs = int(sz.max())

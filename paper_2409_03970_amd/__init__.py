@@ -21,7 +21,7 @@ __all__ = [
     "sort", "sort_pairs", "sort_runs", "merge_pass", "corank", "segmented_sort",
     "segmented_sort_pairs", "cdf_forward", "cdf_backward", "cdf_adam_step", "cdf_train",
     "hvms_cdf_sample_i32", "cdf_sample", "fit_cdf_model", "segmented_sort_pairs_grouped",
-    "segment_groups", "hvms_sort_u32", "hvms_sort_f32", "hvms_sort_pairs_u32",
+    "segment_groups", "grouped_workspace_bytes", "hvms_sort_u32", "hvms_sort_f32", "hvms_sort_pairs_u32",
     "hvms_sort_pairs_f32", "sort_keys", "sort_pairs_keys", "hvms_sort_i64", "hvms_sort_u64",
     "hvms_sort_f64", "hvms_sort_by_key_i32_p64", "sort_by_key",
 ]
@@ -539,13 +539,28 @@ def segment_groups(off_host, max_group_keys):
     return groups
 
 
+def grouped_workspace_bytes(offsets, max_group_keys=1 << 30, opts=None):
+    """Workspace bytes segmented_sort_pairs_grouped needs for these offsets."""
+    off_host = offsets.cpu().tolist() if hasattr(offsets, "cpu") else list(offsets)
+    groups = segment_groups(off_host, max_group_keys)
+    sizes = [off_host[i + 1] - off_host[i] for i in range(len(off_host) - 1)]
+    max_seg = max(sizes) if sizes else 0
+    gmax = max((off_host[s1] - base for s0, s1, base in groups), default=0)
+    smax = max((s1 - s0 for s0, s1, base in groups), default=0)
+    return lib().hvms_segmented_workspace_bytes(gmax, smax, max_seg, 1,
+                                                _opts(opts if opts is not None else {}))
+
+
 def segmented_sort_pairs_grouped(keys, vals, offsets, max_group_keys=1 << 30, opts=None,
-                                 stream=None, opts_for_group=None):
+                                 stream=None, opts_for_group=None, ws=None):
     """In-place segmented pair sort with bounded scratch: the segments are
     sorted group by group (each group one batched call), so the workspace
     holds scratch for one group instead of the whole array.  opts_for_group,
     if given, is called as opts_for_group(keys_view, group_index) and returns
-    the options of that group's call (e.g. a CDF model trained on it)."""
+    the options of that group's call (e.g. a CDF model trained on it).  ws:
+    an optional preallocated uint8 device tensor of at least
+    grouped_workspace_bytes(offsets, max_group_keys, opts) bytes (else one is
+    allocated here)."""
     off_host = offsets.cpu().tolist()
     d_off = offsets.to(keys.device) if not offsets.is_cuda else offsets
     groups = segment_groups(off_host, max_group_keys)
@@ -554,8 +569,11 @@ def segmented_sort_pairs_grouped(keys, vals, offsets, max_group_keys=1 << 30, op
     gmax = max((off_host[s1] - base for s0, s1, base in groups), default=0)
     smax = max((s1 - s0 for s0, s1, base in groups), default=0)
     o0 = opts if opts is not None else {}
-    ws = _workspace(lib().hvms_segmented_workspace_bytes(gmax, smax, max_seg, 1, _opts(o0)),
-                    keys.device)
+    need = lib().hvms_segmented_workspace_bytes(gmax, smax, max_seg, 1, _opts(o0))
+    if ws is None:
+        ws = _workspace(need, keys.device)
+    elif ws.numel() < need:
+        raise ValueError(f"workspace of {ws.numel()} bytes, {need} needed")
     for gi, (s0, s1, base) in enumerate(groups):
         n_g = off_host[s1] - base
         kg = keys[base:base + n_g]

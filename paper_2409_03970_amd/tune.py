@@ -93,7 +93,11 @@ def _time(fn, reps):
 
 
 def tune(op="sort", log2n=24, nseg=200000, seg_max=65536, reps=5, seed=0, path=CACHE,
-         cands=None, verbose=True):
+         cands=None, verbose=True, dists=("uniform",)):
+    """Times every candidate (and the defaults) on the operation's workload
+    and records the fastest in the cache.  dists (sort / sort_pairs): the key
+    distributions the objective sums over, each a separate input of 2^log2n
+    keys; every candidate must reproduce the defaults' outputs exactly."""
     import paper_2409_03970_amd as hv
     from paper_2409_03970_amd import inputs
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -114,18 +118,23 @@ def tune(op="sort", log2n=24, nseg=200000, seg_max=65536, reps=5, seed=0, path=C
         outputs = (out,)
     elif op in ("sort", "sort_pairs"):
         n = 1 << log2n
-        keys = inputs.keys(n, "uniform", seed=seed, device=dev)
+        keyset = [inputs.keys(n, d, seed=seed, device=dev) for d in dists]
         vals = torch.arange(n, device=dev, dtype=torch.int32)
-        out = torch.empty_like(keys)
+        outs = [torch.empty_like(keyset[0]) for _ in dists]
         vout = torch.empty_like(vals)
 
         def run(o):
             pairs = op == "sort_pairs"
             ws = hv._workspace(hv.lib().hvms_sort_workspace_bytes(n, int(pairs), hv._opts(o)), dev)
-            if pairs:
-                return lambda: hv.hvms_sort_pairs_i32(keys, vals, out, vout, ws, opts=o)
-            return lambda: hv.hvms_sort_i32(keys, out, ws, opts=o)
-        outputs = (out, vout) if op == "sort_pairs" else (out,)
+
+            def go():
+                for keys, out in zip(keyset, outs):
+                    if pairs:
+                        hv.hvms_sort_pairs_i32(keys, vals, out, vout, ws, opts=o)
+                    else:
+                        hv.hvms_sort_i32(keys, out, ws, opts=o)
+            return go
+        outputs = tuple(outs) + ((vout,) if op == "sort_pairs" else ())
     else:
         raise ValueError(op)
 
@@ -151,6 +160,8 @@ def tune(op="sort", log2n=24, nseg=200000, seg_max=65536, reps=5, seed=0, path=C
     cache = load_cache(path)
     entry = {"options": best, "ms": best_ms, "default_ms": base_ms, "n": n,
              "candidates": len(results)}
+    if op != "segmented":
+        entry["dists"] = list(dists)
     # the best configuration with two-way passes only, for comparison
     two = next((r for r in results if r[1].get("merge_ways", 2) == 2), None)
     if two is not None:
@@ -171,8 +182,11 @@ def main():
     ap.add_argument("--nseg", type=int, default=200000)
     ap.add_argument("--seg-max", type=int, default=65536)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--dists", default="uniform",
+                    help="comma-separated key distributions whose total time is minimised "
+                         "(sort / sort_pairs), e.g. uniform,gaussian,sorted,reverse,distinct16,zipf")
     a = ap.parse_args()
-    tune(a.op, a.log2n, a.nseg, a.seg_max, a.reps)
+    tune(a.op, a.log2n, a.nseg, a.seg_max, a.reps, dists=tuple(a.dists.split(",")))
 
 
 if __name__ == "__main__":

@@ -197,3 +197,14 @@ def test_corank_stats_summary_percentiles():
     assert r["fallback_rate"] == 0.05 and r["abs_err_mean"] == 7.0
     w[8 + 20] = 5                                       # 5 % at 20 probes: p99 -> 20
     assert hv.corank_stats(w)["probes_p99"] == 20
+
+
+def test_grouped_sort_checks_a_caller_workspace_first():
+    import torch
+    offs = torch.tensor([0, 5000, 9000, 20000], dtype=torch.int64)
+    need = hv.grouped_workspace_bytes(offs, max_group_keys=10000)
+    assert need > 0
+    k = torch.zeros(20000, dtype=torch.int32)
+    with pytest.raises(ValueError):
+        hv.segmented_sort_pairs_grouped(k, k.clone(), offs, max_group_keys=10000,
+                                        ws=torch.empty(need - 1, dtype=torch.uint8))

@@ -172,7 +172,8 @@ def test_grouped_pairs_match_oracle():
     offs = inputs.offsets_from_sizes(sizes)
     k, v = inputs.segment_pairs(sizes, dists, 0, seed=11, device=DEV)
     ek, ev = oracle.segmented_sort_pairs(k.cpu().numpy(), v.cpu().numpy(), offs.numpy())
-    hv.segmented_sort_pairs_grouped(k, v, offs, max_group_keys=200000)
+    ws = hv._workspace(hv.grouped_workspace_bytes(offs, max_group_keys=200000), k.device)
+    hv.segmented_sort_pairs_grouped(k, v, offs, max_group_keys=200000, ws=ws)
     assert np.array_equal(k.cpu().numpy(), ek) and np.array_equal(v.cpu().numpy(), ev)
 
 
