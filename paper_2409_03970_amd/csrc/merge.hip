@@ -20,14 +20,14 @@ namespace hvms {
 // the four run endpoints of each of its pairs, one evaluation per thread
 // and round, so every co-rank of a pair shares them.
 template <typename T>
-__global__ __launch_bounds__(256) void pass_corank_kernel(PlainMap map, int64_t run, int64_t tm,
+__global__ __launch_bounds__(64) void pass_corank_kernel(PlainMap map, int64_t run, int64_t tm,
                                                           int64_t *__restrict__ cr, CorankCtl c)
 {
     __shared__ float4 F[256];
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c.mode == 1) {
         const int64_t q0 = (int64_t)blockIdx.x * blockDim.x;
-        const int64_t qlast = q0 + 255 < map.ntiles - 1 ? q0 + 255 : map.ntiles - 1;
+        const int64_t qlast = q0 + blockDim.x - 1 < map.ntiles - 1 ? q0 + blockDim.x - 1 : map.ntiles - 1;
         const int64_t p0 = q0 * tm / (2 * run), p1 = qlast * tm / (2 * run);
         const int np = (int)(p1 - p0 + 1);
         for (int e = threadIdx.x; e < 4 * np; e += blockDim.x) {
@@ -168,12 +168,12 @@ hipError_t launch_pass_corank(bool pairs, const int32_t *kin, const int32_t *vin
     map.ov = nullptr;
     map.n = n;
     map.ntiles = (n + tm - 1) / tm;
-    const unsigned blocks = (unsigned)((map.ntiles + 255) / 256);
+    const unsigned blocks = (unsigned)((map.ntiles + 63) / 64);
     if (pairs)
-        hipLaunchKernelGGL(pass_corank_kernel<int64_t>, dim3(blocks), dim3(256), 0, s, map, run,
+        hipLaunchKernelGGL(pass_corank_kernel<int64_t>, dim3(blocks), dim3(64), 0, s, map, run,
                            tm, cr, ctl);
     else
-        hipLaunchKernelGGL(pass_corank_kernel<int32_t>, dim3(blocks), dim3(256), 0, s, map, run,
+        hipLaunchKernelGGL(pass_corank_kernel<int32_t>, dim3(blocks), dim3(64), 0, s, map, run,
                            tm, cr, ctl);
     return hipGetLastError();
 }

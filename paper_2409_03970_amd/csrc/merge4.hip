@@ -230,7 +230,7 @@ __device__ Quad quad_corank(const Group<T> &G, int64_t d, int64_t tm, const int6
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void quad_corank_kernel(const int32_t *__restrict__ kin,
+__global__ __launch_bounds__(64) void quad_corank_kernel(const int32_t *__restrict__ kin,
                                                           const int32_t *__restrict__ vin,
                                                           int64_t n, int64_t run, int64_t tm,
                                                           int64_t ntiles, int lg4run,
@@ -517,7 +517,10 @@ static hipError_t launch_quad_corank(const int32_t *kin, const int32_t *vin, int
                                      const CorankOpts &o, hipStream_t s)
 {
     const int64_t ntiles = (n + tm - 1) / tm;
-    hipLaunchKernelGGL(quad_corank_kernel<T>, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0,
+    // one thread per tile, one wave per workgroup: the chains of dependent
+    // probes spread over all CUs (256-thread workgroups left half of them
+    // idle at 2^28 keys and measured 3 % slower per sort)
+    hipLaunchKernelGGL(quad_corank_kernel<T>, dim3((unsigned)((ntiles + 63) / 64)), dim3(64), 0,
                        s, kin, vin, n, run, tm, ntiles, ilog2_pow2(4 * run), grid, (Quad *)rec,
                        o.stats);
     return hipGetLastError();

@@ -305,7 +305,7 @@ __global__ __launch_bounds__(NT) void seg_block_kernel(SegParams P, unsigned lon
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void seg_corank_kernel(SegMap map, int64_t run, int64_t tm,
+__global__ __launch_bounds__(64) void seg_corank_kernel(SegMap map, int64_t run, int64_t tm,
                                                          int64_t *__restrict__ cr, CorankCtl c)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -481,12 +481,12 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
         c.stats = a.co.stats;
         c.pair_cdf = nullptr;
         c.pair_first = 0;
-        const unsigned cb = (unsigned)((L.max_tiles + 255) / 256);
+        const unsigned cb = (unsigned)((L.max_tiles + 63) / 64);
         if (pairs)
-            hipLaunchKernelGGL(seg_corank_kernel<int64_t>, dim3(cb), dim3(256), 0, s, map, run,
+            hipLaunchKernelGGL(seg_corank_kernel<int64_t>, dim3(cb), dim3(64), 0, s, map, run,
                                (int64_t)a.TM, cr, c);
         else
-            hipLaunchKernelGGL(seg_corank_kernel<int32_t>, dim3(cb), dim3(256), 0, s, map, run,
+            hipLaunchKernelGGL(seg_corank_kernel<int32_t>, dim3(cb), dim3(64), 0, s, map, run,
                                (int64_t)a.TM, cr, c);
         e = hipGetLastError();
         if (e != hipSuccess)
