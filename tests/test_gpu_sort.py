@@ -338,3 +338,76 @@ def test_sort_powers_of_two_and_neighbours(k):
         x = inputs.keys(n, "zipf", seed=k, device=DEV)
         y = hv.sort(x)
         assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy())), n
+
+
+# -------------------------------------------- presorted and reverse-sorted tiles
+
+def _near_sorted(n, pos, seed, descending=False):
+    """Sorted (or reverse-sorted) keys with the pair at pos swapped, so that
+    exactly one adjacent pair breaks the order."""
+    rng = np.random.default_rng(seed)
+    x = np.sort(rng.integers(-2**31, 2**31, size=n, dtype=np.int64).astype(np.int32))
+    if descending:
+        x = x[::-1].copy()
+    if pos is not None:
+        x[pos], x[pos + 1] = x[pos + 1], x[pos]
+    return x
+
+
+@pytest.mark.parametrize("shape", [(16, 1024), (32, 512), (8, 256)])
+@pytest.mark.parametrize("descending", [False, True])
+def test_presorted_tiles_and_near_misses(shape, descending):
+    R, NT = shape
+    tile = R * NT
+    opts = {"keys_per_lane": R, "block_threads": NT}
+    # swaps: inside a lane's elements (64 apart), across lanes, across waves,
+    # across tiles, at the tile's very start and end
+    for pos in (None, 0, 5, 63, 64 * R - 1, 64 * R, 3 * 64 * R - 1, tile - 2, tile - 1,
+                tile + 100, 2 * tile - 1):
+        x = _near_sorted(4 * tile + 777, pos, seed=R + (pos or 0), descending=descending)
+        _say("presorted", shape, descending, pos)
+        y = hv.sort(torch.from_numpy(x).to(DEV), opts=opts).cpu().numpy()
+        assert np.array_equal(y, np.sort(x)), pos
+        # one tile only (the block stage is the whole sort)
+        x1 = x[:tile]
+        y1 = hv.sort(torch.from_numpy(x1.copy()).to(DEV), opts=opts).cpu().numpy()
+        assert np.array_equal(y1, np.sort(x1)), pos
+
+
+def test_presorted_ties_constants_and_mixed_tiles():
+    rng = np.random.default_rng(5)
+    tile = 16384
+    parts = [np.full(tile, 7, np.int32),                                   # constant tile
+             np.sort(rng.integers(0, 10, tile)).astype(np.int32),          # ties, ascending
+             np.sort(rng.integers(0, 10, tile)).astype(np.int32)[::-1],    # ties, descending
+             rng.integers(-2**31, 2**31, tile, dtype=np.int64).astype(np.int32),  # random
+             np.arange(tile, 0, -1, dtype=np.int32),                       # strictly descending
+             np.concatenate([np.arange(tile // 2), np.arange(tile // 2)]).astype(np.int32)]
+    x = np.concatenate(parts)
+    for opts in ({}, {"keys_per_lane": 32, "block_threads": 512, "merge_ways": 4}):
+        y = hv.sort(torch.from_numpy(x).to(DEV), opts=opts).cpu().numpy()
+        assert np.array_equal(y, np.sort(x))
+
+
+@pytest.mark.parametrize("descending", [False, True])
+def test_presorted_pairs_and_other_key_types(descending):
+    n = 3 * 16384 + 5
+    k = _near_sorted(n, None, seed=9, descending=descending)
+    v = np.arange(n, dtype=np.int32)                    # ties in k keep pair order distinct
+    ko, vo = hv.sort_pairs(torch.from_numpy(k).to(DEV), torch.from_numpy(v).to(DEV))
+    ek, ev = oracle.sort_pairs(k, v)
+    assert np.array_equal(ko.cpu().numpy(), ek) and np.array_equal(vo.cpu().numpy(), ev)
+    # uint32 / float32 / 64-bit keys: the order is checked on the mapped keys
+    u = np.sort(np.random.default_rng(1).integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32))
+    u = u[::-1].copy() if descending else u
+    yu = hv.sort_keys(torch.from_numpy(u.view(np.int32)).to(DEV).view(torch.uint32))
+    assert np.array_equal(yu.view(torch.int32).cpu().numpy().view(np.uint32), oracle.sort_u32(u))
+    f = np.sort(np.random.default_rng(2).standard_normal(n).astype(np.float32))
+    f = f[::-1].copy() if descending else f
+    yf = hv.sort_keys(torch.from_numpy(f).to(DEV))
+    assert np.array_equal(yf.view(torch.int32).cpu().numpy(),
+                          oracle.sort_f32(f).view(np.int32))
+    d = np.sort(np.random.default_rng(3).standard_normal(16384))
+    d = d[::-1].copy() if descending else d
+    yd = hv.sort_keys(torch.from_numpy(d).to(DEV))          # full tiles read packed
+    assert np.array_equal(yd.cpu().numpy().view(np.uint64), oracle.sort_f64(d).view(np.uint64))
