@@ -105,6 +105,25 @@ template <typename T> __device__ __forceinline__ void cmpx(T &a, T &b)
 
 // Cross-lane half of a compare-exchange: this lane keeps the min of its value
 // and its partner's (upper == false) or the max (upper == true).
+//
+// Keys take a per-stage selector instead (keep_sel): the median of
+// (v, p, sel) with sel = INT32_MAX keeps the max and sel = INT32_MIN the min,
+// one v_med3_i32 per element.  The selector is hidden from the optimizer
+// (an empty asm with a register operand, no instruction), which would
+// otherwise turn the median back into min + max + select.
+__device__ __forceinline__ int32_t keep_selector(bool upper)
+{
+    int32_t sel = upper ? 0x7fffffff : (int32_t)0x80000000;
+    asm volatile("" : "+v"(sel));
+    return sel;
+}
+__device__ __forceinline__ int32_t keep_sel(int32_t v, int32_t p, int32_t sel)
+{
+    const int32_t mn = v < p ? v : p;
+    const int32_t mx = v < p ? p : v;
+    const int32_t m = mn > sel ? mn : sel;
+    return mx < m ? mx : m;
+}
 template <typename T> __device__ __forceinline__ T keep(T v, T p, bool upper)
 {
     if constexpr (sizeof(T) == 4) {
@@ -217,9 +236,16 @@ __device__ __forceinline__ void cross_half_cleaners(T (&v)[R], int lane)
 {
     if constexpr (J >= 0) {
         const bool upper = (lane >> J) & 1;
+        if constexpr (sizeof(T) == 4) {
+            const int32_t sel = keep_selector(upper);
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            v[r] = keep(v[r], xlane<(1 << J)>(v[r]), upper);
+            for (int r = 0; r < R; ++r)
+                v[r] = keep_sel(v[r], xlane<(1 << J)>(v[r]), sel);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[r] = keep(v[r], xlane<(1 << J)>(v[r]), upper);
+        }
         cross_half_cleaners<R, J - 1>(v, lane);
     }
 }
@@ -244,9 +270,16 @@ __device__ __forceinline__ void wave_merge_level(T (&v)[R], int lane)
 #pragma unroll
     for (int r = 0; r < R; ++r)
         p[r] = xlane<FLIP>(v[R - 1 - r]);
+    if constexpr (sizeof(T) == 4) {
+        const int32_t sel = keep_selector(upper);
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-        v[r] = keep(v[r], p[r], upper);
+        for (int r = 0; r < R; ++r)
+            v[r] = keep_sel(v[r], p[r], sel);
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            v[r] = keep(v[r], p[r], upper);
+    }
     cross_half_cleaners<R, K - 2>(v, lane);
     inlane_half_cleaners<R, R / 2>(v);
 }
