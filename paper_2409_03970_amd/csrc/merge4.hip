@@ -433,9 +433,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
         // level 1: X = A (+) B into M[0, nx), Y = C (+) D into M[nx + VT,
         // cnt + VT), with VT sentinels (the maximum of the order) after each,
         // so that level 2 reads past either run's end without masks.
-        // Thread t produces outputs [t*VT, t*VT + VT) of X followed by Y;
-        // the one thread whose range crosses nx also writes the head of Y,
-        // whose co-rank at diagonal 0 is 0 (no search).
+        // Thread t produces outputs [t*VT, t*VT + VT) of X followed by Y.
+        // The row that crosses nx is cut at nx: its thread merges only the
+        // X part, and the head of Y (fewer than VT outputs, from co-rank 0)
+        // is computed by that thread's wave, one output per lane, so no
+        // thread runs two merges while the others wait at the barrier.
         const int nxw = cur.nx, nyw = cur.cnt - cur.nx;
         {
             const int o = t * VT;
@@ -452,14 +454,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
                 reg_merge<VT>(P, alen, boff, blen, i, diag - i, v);
                 const LdsSkew<T> MW{M, 0};
                 put_row<VT>(MW, isx ? o : o + VT, v, (isx ? nxw : cur.cnt) - o);
-                if (isx && o + VT > nxw && nyw > 0) {
+            }
+            // the head of Y in the row that crosses nx: outputs [0, hy) of
+            // C (+) D; lane k finds output k by its co-rank (at most
+            // log2(VT) + 1 steps) and one comparison
+            const int os = nxw - nxw % VT;  // first output of the crossing row
+            const int hy = (nxw % VT != 0 && nyw > 0)
+                               ? (os + VT < cur.cnt ? os + VT : cur.cnt) - nxw
+                               : 0;
+            if (hy > 0 && (t >> 6) == (os / VT) >> 6) {  // wave-uniform
+                const int k = t & 63;
+                if (k < hy) {
                     const LdsPlain<T> Q{S, cur.base[2]};
-                    reg_merge<VT>(Q, cur.len[2], cur.base[3] - cur.base[2], cur.len[3], 0, 0, v);
-                    const int lim2 = (o + VT < cur.cnt ? o + VT : cur.cnt) - nxw;
-#pragma unroll
-                    for (int k = 0; k < VT; ++k)
-                        if (k < lim2)
-                            MW[nxw + VT + k] = v[k];
+                    const int dq = cur.base[3] - cur.base[2];
+                    const int i = lds_corank(Q, cur.len[2], dq, cur.len[3], k);
+                    const int j = k - i;
+                    // both reads stay inside S (windows are followed by
+                    // their chunk padding and VT spare slots)
+                    const T cv = Q[i], dv = Q[dq + j];
+                    const bool fromC = i < cur.len[2] && (j >= cur.len[3] || !(dv < cv));
+                    const LdsSkew<T> MW{M, 0};
+                    MW[nxw + VT + k] = fromC ? cv : dv;
                 }
             }
             if (t < 2 * VT) {  // sentinels at [nx, nx + VT) and [cnt + VT, cnt + 2 VT)
