@@ -436,8 +436,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
         // Thread t produces outputs [t*VT, t*VT + VT) of X followed by Y.
         // The row that crosses nx is cut at nx: its thread merges only the
         // X part, and the head of Y (fewer than VT outputs, from co-rank 0)
-        // is computed by that thread's wave, one output per lane, so no
-        // thread runs two merges while the others wait at the barrier.
+        // is computed by wave 0, one output per lane, so no thread runs two
+        // merges while the others wait at the barrier.
         const int nxw = cur.nx, nyw = cur.cnt - cur.nx;
         {
             const int o = t * VT;
@@ -462,7 +462,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
             const int hy = (nxw % VT != 0 && nyw > 0)
                                ? (os + VT < cur.cnt ? os + VT : cur.cnt) - nxw
                                : 0;
-            if (hy > 0 && (t >> 6) == (os / VT) >> 6) {  // wave-uniform
+            // wave 0: its lanes search the shortest diagonals, so it has
+            // the slack to take this on before the barrier
+            if (hy > 0 && (t >> 6) == 0) {  // wave-uniform
                 const int k = t & 63;
                 if (k < hy) {
                     const LdsPlain<T> Q{S, cur.base[2]};

@@ -226,8 +226,17 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
 }
 
 // Persistent block stage: one packed task per iteration.
+// Register target of the segmented block stage: at R = 8 (keys) it fits 64
+// VGPRs, which keeps two 1024-thread workgroups per CU; one register over
+// that allocation step halves the occupancy.
+template <int R, typename T> constexpr int seg_block_waves_per_simd()
+{
+    return (R <= 8 && sizeof(T) == 4) ? 8 : 1;
+}
+
 template <int R, int NT, typename T>
-__global__ __launch_bounds__(NT) void seg_block_kernel(SegParams P, unsigned long long *ctrl,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(seg_block_waves_per_simd<R, T>())))
+void seg_block_kernel(SegParams P, unsigned long long *ctrl,
                                                        const Piece *__restrict__ pieces,
                                                        const int32_t *__restrict__ ik,
                                                        const int32_t *__restrict__ iv,
