@@ -383,6 +383,41 @@ __device__ __forceinline__ void serial_merge(const V &S, int alen, int boff, int
     }
 }
 
+// VT consecutive elements from position i of an LDS view.  In the skewed
+// view a run of VT <= 16 crosses at most one 16-element row, whose padding
+// shifts the elements after the crossing by one pad: each element's address
+// is one of two bases plus a constant offset.
+template <int VT, typename T>
+__device__ __forceinline__ void load_run(const LdsPlain<T> &S, int i, T (&x)[VT])
+{
+#pragma unroll
+    for (int k = 0; k < VT; ++k)
+        x[k] = S[i + k];
+}
+template <int VT, typename T>
+__device__ __forceinline__ void load_run(const LdsSkew<T> &S, int i, T (&x)[VT])
+{
+    if constexpr (VT <= 16) {
+        const int p = S.base + i;
+        // bit k of cross: element k lies past the end of p's row
+        uint32_t cross = 0xffffu << (16 - (p & 15));
+        asm("" : "+v"(cross));
+        const T *p0 = S.S + LdsSkew<T>::pos(p);
+#pragma unroll
+        for (int k = 0; k < VT; ++k) {
+            // the bit stays opaque, so that its address takes one bit
+            // extract and one shift-add
+            uint32_t bit = __builtin_amdgcn_ubfe(cross, k, 1);
+            asm("" : "+v"(bit));
+            x[k] = p0[k + LdsSkew<T>::kPad * (int)bit];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < VT; ++k)
+            x[k] = S[i + k];
+    }
+}
+
 // The same VT outputs as serial_merge without a dependent LDS read per
 // output (the hybrid bitonic merge of Sec. 2.4 applied to one thread's share
 // of a merge path): both runs' next VT elements are read at once (positions
@@ -398,11 +433,13 @@ template <int VT, bool MASK = true, typename V, typename T>
 __device__ __forceinline__ void reg_merge(const V &S, int alen, int boff, int blen, int i, int j,
                                           T (&out)[VT])
 {
-    T b[VT];
+    T b[VT], xa[VT], yb[VT];
+    load_run<VT>(S, i, xa);
+    load_run<VT>(S, boff + j, yb);
 #pragma unroll
     for (int k = 0; k < VT; ++k) {
-        const T x = S[i + k];
-        const T y = S[boff + j + k];
+        const T x = xa[k];
+        const T y = yb[k];
         if constexpr (MASK) {
             out[k] = i + k < alen ? x : Traits<T>::kMax;
             b[k] = j + k < blen ? y : Traits<T>::kMax;
