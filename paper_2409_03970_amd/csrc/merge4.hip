@@ -392,10 +392,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
         // no barrier needed here: S was last read by level 1 of the previous
         // tile, and a barrier has followed it since
         const int nc = total_chunks(cur);
+        // a full tile has at least TM/4 chunks: its first VT/4 slots need no
+        // per-lane check (wave-uniform)
+        const bool full = cur.cnt == TM;
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
             const int c = t + NT * q;
-            if (c < nc) {
+            if ((full && q < VT / 4) || c < nc) {
                 if (has_tail && chunk_elem(cur, c) == e_tail)
                     fix_tail<T>(pf[q], kin, vin, e_tail, n);
                 put_chunk<T>(S, c, pf[q]);
@@ -420,8 +423,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
                         : cur.len[3] == cur.cnt ? cur.base[3]
                                                 : -1;
         if (src >= 0) {
-            copy_run<NT, CH, T, PK>(LdsPlain<T>{S, 0}, src, 0, kout, vout, cur.gb + cur.o0,
-                                    cur.cnt, t, xout);
+            if (full)  // constant count: no end checks
+                copy_run<NT, CH, T, PK>(LdsPlain<T>{S, 0}, src, 0, kout, vout, cur.gb + cur.o0,
+                                        TM, t, xout);
+            else
+                copy_run<NT, CH, T, PK>(LdsPlain<T>{S, 0}, src, 0, kout, vout, cur.gb + cur.o0,
+                                        cur.cnt, t, xout);
             lds_barrier();  // the next tile's chunks overwrite S
             if (!more)
                 break;
@@ -441,7 +448,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
         const int nxw = cur.nx, nyw = cur.cnt - cur.nx;
         {
             const int o = t * VT;
-            if (o < cur.cnt) {
+            if (full || o < cur.cnt) {
                 const bool isx = o < nxw;
                 const int diag = isx ? o : o - nxw;
                 const int alen = isx ? cur.len[0] : cur.len[2];
@@ -453,7 +460,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
                 T v[VT];
                 reg_merge<VT>(P, alen, boff, blen, i, diag - i, v);
                 const LdsSkew<T> MW{M, 0};
-                put_row<VT>(MW, isx ? o : o + VT, v, (isx ? nxw : cur.cnt) - o);
+                // in a full tile only the row crossing nx is short, and the
+                // register merge filled its slots past the X part with the
+                // maximum of the order, the value the sentinel slots there
+                // receive anyway: store every row whole
+                if (full)
+                    put_row<VT>(MW, isx ? o : o + VT, v, VT);
+                else
+                    put_row<VT>(MW, isx ? o : o + VT, v, (isx ? nxw : cur.cnt) - o);
             }
             // the head of Y in the row that crosses nx: outputs [0, hy) of
             // C (+) D; lane k finds output k by its co-rank (at most
@@ -499,10 +513,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
         }
         lds_barrier();
         // stage the rows in M (skewed, 16-byte stores), then copy out
-        // coalesced; a tile starts at a multiple of TM, so 16-byte aligned
-        put_row<VT>(MX, diag, out, cur.cnt - diag);
-        lds_barrier();
-        copy_out<NT, CH, T, PK>(MX, kout, vout, cur.gb + cur.o0, cur.cnt, t);
+        // coalesced; a tile starts at a multiple of TM, so 16-byte aligned.
+        // Every tile but the ragged last one of the array is full: its rows
+        // and chunks need no end checks (wave-uniform branch, constant
+        // count).
+        if (full) {
+            put_row<VT>(MX, diag, out, VT);
+            lds_barrier();
+            copy_out<NT, CH, T, PK>(MX, kout, vout, cur.gb + cur.o0, TM, t);
+        } else {
+            put_row<VT>(MX, diag, out, cur.cnt - diag);
+            lds_barrier();
+            copy_out<NT, CH, T, PK>(MX, kout, vout, cur.gb + cur.o0, cur.cnt, t);
+        }
         if (!more)
             break;
         g = gn;
