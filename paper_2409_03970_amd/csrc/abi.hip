@@ -118,7 +118,7 @@ SortWs sort_ws_layout(int64_t n, bool pairs, const Cfg &c, bool packed = false)
     const int64_t ntiles = (n + c.TM - 1) / c.TM;
     w.coranks = off;  // one int64 per tile
     off += align256((ntiles + 2) * 8);
-    if (c.ways == 4) {  // four-way passes: one co-rank record per tile
+    if (c.ways == 4) {  // four-way passes: one window-geometry record per tile
         w.records = off;
         off += align256((ntiles + 2) * (int64_t)merge4_record_bytes());
     }

@@ -9,9 +9,13 @@
 // c = co-rank of d - x in C(+)D.  X and Y are never stored.  The two-way
 // co-ranks of every tile-aligned diagonal of X and of Y (one launch of the
 // two-way co-rank kernel) form a sample grid that confines x to one interval
-// of TM diagonals; a nested bisection finishes inside it.  The merge kernel
-// loads the four windows (TM elements together), merges A with B and C with
-// D in LDS, then the two results, and writes the tile with coalesced stores.
+// of TM diagonals; a nested bisection finishes inside it.  The co-rank
+// kernel turns the co-ranks of a tile's first and next diagonals into the
+// tile's window geometry, one 64-byte record per tile, so that the merge
+// kernel's waves do no 64-bit geometry arithmetic of their own.  The merge
+// kernel loads the four windows (TM elements together), merges A with B and
+// C with D in LDS, then the two results, and writes the tile with coalesced
+// stores.
 #include "hvms_internal.h"
 #include "merge_common.h"
 
@@ -229,31 +233,6 @@ __device__ Quad quad_corank(const Group<T> &G, int64_t d, int64_t tm, const int6
     return q;
 }
 
-template <typename T>
-__global__ __launch_bounds__(64) void quad_corank_kernel(const int32_t *__restrict__ kin,
-                                                          const int32_t *__restrict__ vin,
-                                                          int64_t n, int64_t run, int64_t tm,
-                                                          int64_t ntiles, int lg4run,
-                                                          const int64_t *__restrict__ grid,
-                                                          Quad *__restrict__ out,
-                                                          unsigned long long *stats)
-{
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ntiles)
-        return;
-    const int64_t o0 = g * tm;
-    const int64_t gq = o0 >> lg4run;
-    const Group<T> G = group_of<T>(kin, vin, n, run, gq);
-    const int64_t d = o0 - G.gb;
-    unsigned probes = 0;
-    out[g] = quad_corank<T>(G, d, tm, grid, G.gb / tm, (G.gb + 2 * run) / tm, probes);
-    if (stats) {
-        atomicAdd(stats + 0, 1ull);
-        atomicAdd(stats + 1, (unsigned long long)probes);
-        atomicAdd(stats + 8 + (probes < 63 ? probes : 63), 1ull);
-    }
-}
-
 struct Tile4 {
     int64_t gb, o0;       // group start (absolute), first output (group-relative)
     int64_t al[4];        // absolute index of the first chunk of each window
@@ -310,6 +289,89 @@ __device__ __forceinline__ Tile4 tile4_geo(const Group<T> &G, int64_t run, int64
     return t;
 }
 
+
+// A tile's window geometry as the merge kernel reads it: one 64-byte record
+// per tile, written by the co-rank kernel, so that the merge kernel's waves
+// do no 64-bit geometry arithmetic of their own.  w: len0 | len1 << 16,
+// len2 | len3 << 16, base0 | base1 << 16, base2 | base3 << 16, c1 | c2 << 16,
+// c3 | nc << 16 (c_r: first chunk of window r, nc: chunks in all), cnt, nx.
+struct TileRec {
+    int64_t dl[4];  // chunk c of window r starts at absolute index 4c + dl[r]
+    uint32_t w[8];
+};
+
+// The record as the merge kernel holds it (wave-uniform)
+struct TileW {
+    int64_t dl[4];
+    int cnt, nx;
+    int len[4], base[4];
+    int c1, c2, c3, nc;
+};
+static_assert(sizeof(TileRec) == 64, "one 64-byte record per tile");
+
+__device__ __forceinline__ TileRec tile_rec_of(const Tile4 &t)
+{
+    TileRec r;
+    const int c1 = t.nch[0], c2 = c1 + t.nch[1], c3 = c2 + t.nch[2], nc = c3 + t.nch[3];
+    r.dl[0] = t.al[0];
+    r.dl[1] = t.al[1] - 4 * c1;
+    r.dl[2] = t.al[2] - 4 * c2;
+    r.dl[3] = t.al[3] - 4 * c3;
+    r.w[0] = (uint32_t)t.len[0] | ((uint32_t)t.len[1] << 16);
+    r.w[1] = (uint32_t)t.len[2] | ((uint32_t)t.len[3] << 16);
+    r.w[2] = (uint32_t)t.base[0] | ((uint32_t)t.base[1] << 16);
+    r.w[3] = (uint32_t)t.base[2] | ((uint32_t)t.base[3] << 16);
+    r.w[4] = (uint32_t)c1 | ((uint32_t)c2 << 16);
+    r.w[5] = (uint32_t)c3 | ((uint32_t)nc << 16);
+    r.w[6] = (uint32_t)t.cnt;
+    r.w[7] = (uint32_t)t.nx;
+    return r;
+}
+
+// One wave per workgroup; lane l searches the co-ranks of tile 63 * wave +
+// l, and lanes 0..62 each write their tile's record, taking the next
+// tile's co-ranks from the next lane (lane 63 searches the first tile of
+// the following wave for lane 62, so every wave has all it needs).
+template <typename T>
+__global__ __launch_bounds__(64) void quad_corank_kernel(const int32_t *__restrict__ kin,
+                                                          const int32_t *__restrict__ vin,
+                                                          int64_t n, int64_t run, int64_t tm,
+                                                          int64_t ntiles, int lg4run,
+                                                          const int64_t *__restrict__ grid,
+                                                          TileRec *__restrict__ out,
+                                                          unsigned long long *stats)
+{
+    const int l = threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * 63 + l;
+    Quad q{0, 0, 0};
+    Group<T> G{};
+    if (g < ntiles) {
+        const int64_t o0 = g * tm;
+        G = group_of<T>(kin, vin, n, run, o0 >> lg4run);
+        unsigned probes = 0;
+        q = quad_corank<T>(G, o0 - G.gb, tm, grid, G.gb / tm, (G.gb + 2 * run) / tm, probes);
+        if (stats && l < 63) {
+            atomicAdd(stats + 0, 1ull);
+            atomicAdd(stats + 1, (unsigned long long)probes);
+            atomicAdd(stats + 8 + (probes < 63 ? probes : 63), 1ull);
+        }
+    }
+    // the next tile's co-ranks (for the array's last tile they are unused:
+    // its end is its group's end)
+    auto next = [&](int64_t v) {
+        const int a = ((l + 1) & 63) << 2;
+        const int lo = __builtin_amdgcn_ds_bpermute(a, (int)(uint32_t)v);
+        const int hi = __builtin_amdgcn_ds_bpermute(a, (int)(v >> 32));
+        return (int64_t)(uint32_t)lo | ((int64_t)hi << 32);
+    };
+    Quad q1;
+    q1.x = next(q.x);
+    q1.a = next(q.a);
+    q1.c = next(q.c);
+    if (l < 63 && g < ntiles)
+        out[g] = tile_rec_of(tile4_geo<T>(G, run, tm, g, q, q1));
+}
+
 // PK: the output is one packed 64-bit array at kout (the last pass of a
 // 64-bit key sort).
 template <int NT, int VT, typename T, bool PK = false>
@@ -317,7 +379,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
                                                          const int32_t *__restrict__ vin,
                                                          int32_t *__restrict__ kout,
                                                          int32_t *__restrict__ vout, int64_t n,
-                                                         int64_t run, const Quad *__restrict__ rec,
+                                                         int64_t run, const TileRec *__restrict__ rec,
                                                          int64_t ntiles, int lg4run, KeyMap xout)
 {
     constexpr int TM = NT * VT;
@@ -333,44 +395,45 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
     if (first >= last)
         return;
 
-    // records of tile g and g + 1: six int64 words, one per lane 0..5
-    const int64_t *words = (const int64_t *)rec;
-    auto load_rec = [&](int64_t g) -> int64_t {
-        const int l = t & 7;
-        const int64_t gi = g + (l >= 3 ? 1 : 0);
-        const int64_t w = (gi < ntiles ? gi : ntiles - 1) * 3 + (l % 3);
-        return words[w];
-    };
-    auto rd = [](int64_t v, int lane) {
-        return (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane) |
-               ((int64_t)__builtin_amdgcn_readlane((int)(v >> 32), lane) << 32);
-    };
-    auto geo_of = [&](int64_t g, int64_t rv) {
-        Quad q0, q1;
-        q0.x = rd(rv, 0);
-        q0.a = rd(rv, 1);
-        q0.c = rd(rv, 2);
-        q1.x = rd(rv, 3);
-        q1.a = rd(rv, 4);
-        q1.c = rd(rv, 5);
-        // runs and tiles are powers of two: the group index is a shift
-        const Group<T> G = group_of<T>(kin, vin, n, run, (g * TM) >> lg4run);
-        return tile4_geo<T>(G, run, TM, g, q0, q1);
+    // tile g's record: one 32-bit word per lane 0..15 (a vector load, so
+    // that waiting for it never waits for LDS traffic)
+    const uint32_t *words = (const uint32_t *)rec;
+    auto load_rec = [&](int64_t g) -> uint32_t { return words[g * 16 + (t & 15)]; };
+    auto geo_of = [&](uint32_t rv) {
+        auto rl = [&](int lane) { return (uint32_t)__builtin_amdgcn_readlane((int)rv, lane); };
+        TileW w;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            w.dl[r] = (int64_t)((uint64_t)rl(2 * r) | ((uint64_t)rl(2 * r + 1) << 32));
+        const uint32_t l01 = rl(8), l23 = rl(9), b01 = rl(10), b23 = rl(11), c12 = rl(12),
+                       c3n = rl(13);
+        w.len[0] = (int)(l01 & 0xffff);
+        w.len[1] = (int)(l01 >> 16);
+        w.len[2] = (int)(l23 & 0xffff);
+        w.len[3] = (int)(l23 >> 16);
+        w.base[0] = (int)(b01 & 0xffff);
+        w.base[1] = (int)(b01 >> 16);
+        w.base[2] = (int)(b23 & 0xffff);
+        w.base[3] = (int)(b23 >> 16);
+        w.c1 = (int)(c12 & 0xffff);
+        w.c2 = (int)(c12 >> 16);
+        w.c3 = (int)(c3n & 0xffff);
+        w.nc = (int)(c3n >> 16);
+        w.cnt = (int)rl(14);
+        w.nx = (int)rl(15);
+        return w;
     };
 
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int64_t e_tail = n & ~(int64_t)3;
     const bool has_tail = (n & 3) != 0;
-    auto chunk_elem = [&](const Tile4 &G, int c) -> int64_t {
-        const int c1 = G.nch[0], c2 = c1 + G.nch[1], c3 = c2 + G.nch[2];
-        return c < c1   ? G.al[0] + 4 * c
-               : c < c2 ? G.al[1] + 4 * (c - c1)
-               : c < c3 ? G.al[2] + 4 * (c - c2)
-                        : G.al[3] + 4 * (c - c3);
+    auto chunk_elem = [&](const TileW &G, int c) -> int64_t {
+        const int64_t d = c < G.c1 ? G.dl[0] : c < G.c2 ? G.dl[1] : c < G.c3 ? G.dl[2] : G.dl[3];
+        return d + 4 * c;
     };
-    auto total_chunks = [](const Tile4 &G) { return G.nch[0] + G.nch[1] + G.nch[2] + G.nch[3]; };
+    auto total_chunks = [](const TileW &G) { return G.nc; };
     Chunk<T> pf[CH];
-    auto prefetch = [&](const Tile4 &G) {
+    auto prefetch = [&](const TileW &G) {
         const int nc = total_chunks(G);
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
@@ -384,9 +447,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
     };
 
     int64_t g = first;
-    Tile4 cur = geo_of(g, load_rec(g));
+    TileW cur = geo_of(load_rec(g));
     prefetch(cur);
-    int64_t rn = g + step < last ? load_rec(g + step) : 0;
+    uint32_t rn = g + step < last ? load_rec(g + step) : 0;
 
     for (;;) {
         // no barrier needed here: S was last read by level 1 of the previous
@@ -408,9 +471,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
 
         const int64_t gn = g + step;
         const bool more = gn < last;
-        Tile4 nxt;
+        TileW nxt;
         if (more) {
-            nxt = geo_of(gn, rn);
+            nxt = geo_of(rn);
             prefetch(nxt);
             rn = gn + step < last ? load_rec(gn + step) : 0;
         }
@@ -424,10 +487,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
                                                 : -1;
         if (src >= 0) {
             if (full)  // constant count: no end checks
-                copy_run<NT, CH, T, PK>(LdsPlain<T>{S, 0}, src, 0, kout, vout, cur.gb + cur.o0,
+                copy_run<NT, CH, T, PK>(LdsPlain<T>{S, 0}, src, 0, kout, vout, g * TM,
                                         TM, t, xout);
             else
-                copy_run<NT, CH, T, PK>(LdsPlain<T>{S, 0}, src, 0, kout, vout, cur.gb + cur.o0,
+                copy_run<NT, CH, T, PK>(LdsPlain<T>{S, 0}, src, 0, kout, vout, g * TM,
                                         cur.cnt, t, xout);
             lds_barrier();  // the next tile's chunks overwrite S
             if (!more)
@@ -520,11 +583,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
         if (full) {
             put_row<VT>(MX, diag, out, VT);
             lds_barrier();
-            copy_out<NT, CH, T, PK>(MX, kout, vout, cur.gb + cur.o0, TM, t);
+            copy_out<NT, CH, T, PK>(MX, kout, vout, g * TM, TM, t);
         } else {
             put_row<VT>(MX, diag, out, cur.cnt - diag);
             lds_barrier();
-            copy_out<NT, CH, T, PK>(MX, kout, vout, cur.gb + cur.o0, cur.cnt, t);
+            copy_out<NT, CH, T, PK>(MX, kout, vout, g * TM, cur.cnt, t);
         }
         if (!more)
             break;
@@ -549,7 +612,7 @@ bool merge4_supported(int tm, bool pairs)
     return pairs ? (tm == 2048 || tm == 4096) : (tm == 4096 || tm == 8192 || tm == 16384);
 }
 
-size_t merge4_record_bytes() { return sizeof(Quad); }
+size_t merge4_record_bytes() { return sizeof(TileRec); }
 
 template <typename T>
 static hipError_t launch_quad_corank(const int32_t *kin, const int32_t *vin, int64_t n,
@@ -560,8 +623,8 @@ static hipError_t launch_quad_corank(const int32_t *kin, const int32_t *vin, int
     // one thread per tile, one wave per workgroup: the chains of dependent
     // probes spread over all CUs (256-thread workgroups left half of them
     // idle at 2^28 keys and measured 3 % slower per sort)
-    hipLaunchKernelGGL(quad_corank_kernel<T>, dim3((unsigned)((ntiles + 63) / 64)), dim3(64), 0,
-                       s, kin, vin, n, run, tm, ntiles, ilog2_pow2(4 * run), grid, (Quad *)rec,
+    hipLaunchKernelGGL(quad_corank_kernel<T>, dim3((unsigned)((ntiles + 62) / 63)), dim3(64), 0,
+                       s, kin, vin, n, run, tm, ntiles, ilog2_pow2(4 * run), grid, (TileRec *)rec,
                        o.stats);
     return hipGetLastError();
 }
@@ -582,7 +645,7 @@ static hipError_t launch_m4_1(const int32_t *kin, const int32_t *vin, int32_t *k
     if (grid > ntiles)
         grid = ntiles;
     hipLaunchKernelGGL((merge4_pipe_kernel<NT, VT, T, PK>), dim3((unsigned)grid), dim3(NT), 0, s,
-                       kin, vin, kout, vout, n, run, (const Quad *)rec, ntiles, ilog2_pow2(4 * run),
+                       kin, vin, kout, vout, n, run, (const TileRec *)rec, ntiles, ilog2_pow2(4 * run),
                        xout);
     return hipGetLastError();
 }
