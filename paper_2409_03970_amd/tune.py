@@ -67,8 +67,11 @@ def candidates(op):
     if op == "sort":
         shapes.append((32, 1024))
     out = []
-    for (R, NT), K, TM, V, W in itertools.product(shapes, (6, 5, 4), (4096, 8192), (2, 3), (2, 4)):
+    for (R, NT), K, TM, V, W in itertools.product(shapes, (6, 5, 4), (4096, 8192, 16384), (2, 3),
+                                                  (2, 4)):
         if TM > 2 * R * NT:
+            continue
+        if TM == 16384 and (op != "sort" or W != 4):  # four-way key passes only
             continue
         if op != "sort" and R * NT * 8 > 163840:
             continue
@@ -185,8 +188,9 @@ def main():
     ap.add_argument("--dists", default="uniform",
                     help="comma-separated key distributions whose total time is minimised "
                          "(sort / sort_pairs), e.g. uniform,gaussian,sorted,reverse,distinct16,zipf")
+    ap.add_argument("--path", default=CACHE, help="tuning cache to update (default: the package's)")
     a = ap.parse_args()
-    tune(a.op, a.log2n, a.nseg, a.seg_max, a.reps, dists=tuple(a.dists.split(",")))
+    tune(a.op, a.log2n, a.nseg, a.seg_max, a.reps, path=a.path, dists=tuple(a.dists.split(",")))
 
 
 if __name__ == "__main__":
