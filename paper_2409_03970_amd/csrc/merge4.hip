@@ -372,6 +372,31 @@ __global__ __launch_bounds__(64) void quad_corank_kernel(const int32_t *__restri
         out[g] = tile_rec_of(tile4_geo<T>(G, run, tm, g, q, q1));
 }
 
+// VT consecutive outputs of one thread from registers to absolute index e
+// (a multiple of 4), as 16-byte stores; pairs are split into the key and
+// value arrays, or stored whole when the output is packed (PK).
+template <int VT, typename T, bool PK>
+__device__ __forceinline__ void store_run(int32_t *__restrict__ k, int32_t *__restrict__ v,
+                                          int64_t e, const T (&x)[VT])
+{
+#pragma unroll
+    for (int q = 0; q < VT; q += 4) {
+        if constexpr (sizeof(T) == 4) {
+            *(int4 *)(k + e + q) = make_int4(x[q], x[q + 1], x[q + 2], x[q + 3]);
+        } else if constexpr (PK) {
+            typedef int64_t V2 __attribute__((ext_vector_type(2)));
+            V2 *o = (V2 *)((int64_t *)k + e + q);
+            o[0] = V2{x[q], x[q + 1]};
+            o[1] = V2{x[q + 2], x[q + 3]};
+        } else {
+            *(int4 *)(k + e + q) =
+                make_int4(pair_key(x[q]), pair_key(x[q + 1]), pair_key(x[q + 2]), pair_key(x[q + 3]));
+            *(int4 *)(v + e + q) =
+                make_int4(pair_val(x[q]), pair_val(x[q + 1]), pair_val(x[q + 2]), pair_val(x[q + 3]));
+        }
+    }
+}
+
 // PK: the output is one packed 64-bit array at kout (the last pass of a
 // 64-bit key sort).
 template <int NT, int VT, typename T, bool PK = false>
@@ -574,17 +599,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
             for (int k = 0; k < VT; ++k)
                 out[k] = map_elem(out[k], xout);
         }
-        lds_barrier();
-        // stage the rows in M (skewed, 16-byte stores), then copy out
-        // coalesced; a tile starts at a multiple of TM, so 16-byte aligned.
-        // Every tile but the ragged last one of the array is full: its rows
-        // and chunks need no end checks (wave-uniform branch, constant
-        // count).
+        // Every tile but the ragged last one of the array is full: each
+        // thread's VT outputs are consecutive in the output, and it stores
+        // them from registers (16-byte stores; a tile starts at a multiple
+        // of TM).  No LDS is written after level 2, so neither barrier of
+        // the staged copy is needed: the next tile writes S (last read
+        // before this tile's second barrier) and then, after its first
+        // barrier, M.  A ragged tile stages its rows in M (skewed) and
+        // copies out the first cnt outputs.
         if (full) {
-            put_row<VT>(MX, diag, out, VT);
-            lds_barrier();
-            copy_out<NT, CH, T, PK>(MX, kout, vout, g * TM, TM, t);
+            store_run<VT, T, PK>(kout, vout, g * TM + diag, out);
         } else {
+            lds_barrier();
             put_row<VT>(MX, diag, out, cur.cnt - diag);
             lds_barrier();
             copy_out<NT, CH, T, PK>(MX, kout, vout, g * TM, cur.cnt, t);
