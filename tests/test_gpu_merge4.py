@@ -27,6 +27,19 @@ def test_four_way_level_counts_and_partial_groups(tiles, tm):
     _check(x, {"keys_per_lane": 16, "block_threads": 256, "merge_tile": tm, "merge_ways": 4})
 
 
+@pytest.mark.parametrize("tiles", [62, 63, 64, 65, 126, 127, 128, 190])
+@pytest.mark.parametrize("dist", ["uniform", "sorted", "reverse", "distinct16"])
+def test_four_way_tile_records_across_wave_boundaries(tiles, dist):
+    # the co-rank kernel writes each tile's geometry record from its own
+    # co-ranks and the next tile's (the next lane's; every 64-lane wave owns
+    # 63 tiles): tile counts on both sides of multiples of 63, full and
+    # ragged last tiles
+    for ragged in (0, 777):
+        n = tiles * 4096 - ragged
+        x = inputs.keys(n, dist, seed=tiles, device=DEV)
+        _check(x, {"keys_per_lane": 16, "block_threads": 256, "merge_tile": 4096, "merge_ways": 4})
+
+
 @pytest.mark.parametrize("dist", list(inputs.DISTRIBUTIONS) + ["mixture"])
 @pytest.mark.parametrize("mode", [hv.CORANK_BINARY, hv.CORANK_LINEAR])
 def test_four_way_distributions(dist, mode):
