@@ -471,12 +471,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
         }
     };
 
+    // records stay undecoded in a VGPR until their tile comes up (rc: this
+    // tile, rn: the next); the prefetch decodes only what it needs, so no
+    // second decoded tile is held in scalar registers across the loop
     int64_t g = first;
-    TileW cur = geo_of(load_rec(g));
-    prefetch(cur);
+    uint32_t rc = load_rec(g);
+    prefetch(geo_of(rc));
     uint32_t rn = g + step < last ? load_rec(g + step) : 0;
 
     for (;;) {
+        const TileW cur = geo_of(rc);
         // no barrier needed here: S was last read by level 1 of the previous
         // tile, and a barrier has followed it since
         const int nc = total_chunks(cur);
@@ -496,10 +500,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
 
         const int64_t gn = g + step;
         const bool more = gn < last;
-        TileW nxt;
+        const uint32_t rnext = rn;
         if (more) {
-            nxt = geo_of(rn);
-            prefetch(nxt);
+            prefetch(geo_of(rn));
             rn = gn + step < last ? load_rec(gn + step) : 0;
         }
 
@@ -521,7 +524,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
             if (!more)
                 break;
             g = gn;
-            cur = nxt;
+            rc = rnext;
             continue;
         }
 
@@ -618,7 +621,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
         if (!more)
             break;
         g = gn;
-        cur = nxt;
+        rc = rnext;
     }
 }
 
