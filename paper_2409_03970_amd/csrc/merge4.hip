@@ -14,8 +14,9 @@
 // tile's window geometry, one 64-byte record per tile, so that the merge
 // kernel's waves do no 64-bit geometry arithmetic of their own.  The merge
 // kernel loads the four windows (TM elements together), merges A with B and
-// C with D in LDS, then the two results, and writes the tile with coalesced
-// stores.
+// C with D in LDS, then the two results, and writes a full tile from
+// registers (each thread's outputs are consecutive) and the array's ragged
+// last tile through LDS with coalesced stores.
 #include "hvms_internal.h"
 #include "merge_common.h"
 
