@@ -141,16 +141,27 @@ int64_t hvms_sort_workspace_bytes(int64_t n, int32_t pairs, const hvms_options *
 int hvms_sort_i32(const int32_t *d_in, int32_t *d_out, int64_t n, void *d_ws,
                   size_t ws_bytes, void *stream, const hvms_options *opt);
 
-/* Sort n (key, value) pairs lexicographically (keys and values are separate
- * int32 arrays; outputs may alias the matching inputs). */
+/*
+ * Sort n (key, value) pairs: the same merge sort (Sec. 2.1-2.4) with each
+ * value carried beside its key.  The paper sorts keys alone; here every
+ * comparison is on (key, value), both signed int32, lexicographically, the
+ * one order that a comparator network meets bit-exactly (it equals a stable
+ * sort by key when the values are the input positions).
+ *   d_keys_in, d_vals_in    device int32 arrays of n elements.
+ *   d_keys_out, d_vals_out  device int32 arrays of n elements; each may be
+ *                           the matching input (in place).
+ *   d_ws/ws_bytes           workspace, >= hvms_sort_workspace_bytes(n, 1, opt),
+ *                           256-byte aligned.
+ * n == 0 is a no-op.  Errors as hvms_sort_i32.
+ */
 int hvms_sort_pairs_i32(const int32_t *d_keys_in, const int32_t *d_vals_in,
                         int32_t *d_keys_out, int32_t *d_vals_out, int64_t n,
                         void *d_ws, size_t ws_bytes, void *stream,
                         const hvms_options *opt);
 
 /*
- * Other 32-bit key types (the paper sorts 32-bit integers "as an example",
- * Sec. 2.1): the same sort with an order-preserving bit map of the keys onto
+ * Other 32-bit key types (Sec. 2.2 works with 32-bit integers and presents
+ * them as one choice of key): the same sort with an order-preserving bit map of the keys onto
  * int32 order applied as the keys are first loaded and undone as they are
  * finally stored, so no pass over memory is added.
  *   hvms_sort_u32:  unsigned order.
@@ -177,7 +188,9 @@ int hvms_sort_pairs_f32(const float *d_keys_in, const int32_t *d_vals_in,
                         const hvms_options *opt);
 
 /*
- * 64-bit keys (the 64-bit key types of the same sort).  Each key is handled
+ * 64-bit keys: the merge sort of Sec. 2.1-2.4 over 64-bit elements (the
+ * paper's 32-bit integers widened; its comparator of Fig. 3 compares whole
+ * elements whatever their width).  Each key is handled
  * as one 64-bit element: the key-value machinery of hvms_sort_pairs_i32 orders
  * (high word, low word) lexicographically, and a 64-bit key in that form
  * (low word with its sign bit flipped) compares exactly as the signed 64-bit
@@ -207,7 +220,8 @@ int hvms_sort_f64(const double *d_in, double *d_out, int64_t n, void *d_ws,
                   size_t ws_bytes, void *stream, const hvms_options *opt);
 
 /*
- * 64-bit payloads: a stable sort of int32 keys carrying one 64-bit value each
+ * 64-bit payloads: a stable sort of int32 keys (the merge sort of Sec. 2.1-2.4
+ * on (key, input index) pairs) carrying one 64-bit value each
  * (any 8-byte type: int64, uint64, double, a pointer).  d_keys_out is the
  * ascending arrangement of d_keys_in; d_vals_out[i] is the payload that
  * came with d_keys_out[i]; keys that are equal keep their input order.  The
@@ -231,8 +245,8 @@ int hvms_sort_by_key_i32_p64(const int32_t *d_keys_in, const uint64_t *d_vals_in
 
 /*
  * Sort every run of 2^run_log2 consecutive keys independently (the last run
- * may be shorter): the block stage alone, i.e. "every X elements in order"
- * of Table 2 with X = 2^run_log2.  run_log2 must lie in
+ * may be shorter): the block stage alone, i.e. the sorted runs of X keys that
+ * Table 2 times, with X = 2^run_log2.  run_log2 must lie in
  * [log2(keys_per_lane), log2(block tile)].  Uses no workspace.
  */
 int hvms_sort_runs_i32(const int32_t *d_in, int32_t *d_out, int64_t n, int32_t run_log2,
@@ -269,16 +283,23 @@ int hvms_corank_i32(const int32_t *d_a, int64_t m, const int32_t *d_b, int64_t k
  * d_in[off[s] .. off[s+1]) to d_out at the same positions.
  *   d_offsets  DEVICE array of nseg+1 nondecreasing int64 offsets.
  *   n_total    must equal off[nseg] (the arrays hold at least n_total keys).
- *   max_seg    host-side upper bound on the largest segment; it fixes how
- *              many merge passes are enqueued, so a segment larger than it is
- *              left unsorted.
+ *   max_seg    host-side upper bound on the largest segment, or negative if
+ *              none is known.  It fixes how many merge passes are enqueued:
+ *              ceil(log2(ceil(max_seg / block tile))), from n_total when
+ *              negative (a few empty launches more).  A segment larger than
+ *              the bound is NOT fully sorted: it comes out as a permutation
+ *              of its input made of sorted runs of block tile * 2^passes keys,
+ *              and it is counted in status word 0 (hvms_segmented_status).
  *   d_out      16-byte aligned (pairs: d_vals_out too).
  * Elements outside [off[0], off[nseg]) are not written.  A segment whose
- * offsets fall outside [0, n_total] is treated as empty.  Everything up to
- * the block tile is sorted by one persistent launch that pulls packed tasks
- * from an atomic ticket; larger segments add one co-rank and one merge launch
- * per merge pass.  The call allocates and synchronises nothing, so it can be
- * captured into a hipGraph.  Workspace: hvms_segmented_workspace_bytes.
+ * offsets fall outside [0, n_total] or decrease is treated as empty and
+ * counted in status word 1.  If the sizes add up to more than n_total
+ * allows, nothing is sorted or written and status word 2 is set.
+ * Everything up to the block tile is sorted by one persistent launch that
+ * pulls packed tasks from an atomic ticket; larger segments add one co-rank
+ * and one merge launch per merge pass.  The call allocates and synchronises
+ * nothing, so it can be captured into a hipGraph.  Workspace:
+ * hvms_segmented_workspace_bytes.
  */
 int64_t hvms_segmented_workspace_bytes(int64_t n_total, int64_t nseg, int64_t max_seg,
                                        int32_t pairs, const hvms_options *opt);
@@ -290,6 +311,19 @@ int hvms_segmented_sort_pairs_i32(const int32_t *d_keys_in, const int32_t *d_val
                                   const int64_t *d_offsets, int64_t nseg, int64_t n_total,
                                   int64_t max_seg, void *d_ws, size_t ws_bytes,
                                   void *stream, const hvms_options *opt);
+
+/*
+ * Status of the last segmented call that used workspace d_ws (the same
+ * workspace pointer, after that call): enqueues on `stream` a copy of three
+ * int64 words to device memory d_status[0..3):
+ *   [0] segments larger than the max_seg bound allowed (left as sorted runs);
+ *   [1] segments skipped for invalid offsets;
+ *   [2] 1 if the offsets were inconsistent with n_total (nothing was sorted).
+ * All zero means every segment was sorted.  The words belong to the last
+ * call on that workspace, so read them before the workspace is reused.
+ * Returns HVMS_ERR_INVALID_ARG for a null or misaligned pointer.
+ */
+int hvms_segmented_status(const void *d_ws, int64_t *d_status, void *stream);
 
 /* -------------------------------------------------------- learned co-rank */
 

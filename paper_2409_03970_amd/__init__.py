@@ -7,7 +7,10 @@ kernels.  torch only provides device memory and streams.  Importing this
 package does not load the library; the first call does, and raises if the
 library has not been built (python -m paper_2409_03970_amd.build).
 """
+import contextlib
 import ctypes
+import functools
+import inspect
 import os
 
 import torch
@@ -23,7 +26,7 @@ __all__ = [
     "hvms_cdf_sample_i32", "cdf_sample", "fit_cdf_model", "segmented_sort_pairs_grouped",
     "segment_groups", "grouped_workspace_bytes", "hvms_sort_u32", "hvms_sort_f32", "hvms_sort_pairs_u32",
     "hvms_sort_pairs_f32", "sort_keys", "sort_pairs_keys", "hvms_sort_i64", "hvms_sort_u64",
-    "hvms_sort_f64", "hvms_sort_by_key_i32_p64", "sort_by_key",
+    "hvms_sort_f64", "hvms_sort_by_key_i32_p64", "sort_by_key", "hvms_segmented_status",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -137,6 +140,7 @@ _SIGS = {
     "hvms_cdf_train_workspace_bytes": ([_i64], _i64),
     "hvms_cdf_train": ([_vp, _vp, _vp, _vp, _i64, _i64, _i32, _f32, _u64, _vp, _sz, _vp], _i32),
     "hvms_cdf_sample_i32": ([_vp, _i64, _i64, _u64, _vp, _vp], _i32),
+    "hvms_segmented_status": ([_vp, _vp, _vp], _i32),
 }
 
 _lib = None
@@ -164,6 +168,29 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return _vp(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _on(stream):
+    """Context for the allocating conveniences: tensors they allocate (the
+    workspace, temporaries, outputs) belong to the stream the library's
+    kernels run on, so the caching allocator never hands that memory to
+    other work before those kernels are done with it."""
+    if stream is None:
+        return contextlib.nullcontext()
+    if not isinstance(stream, torch.cuda.Stream):
+        stream = torch.cuda.ExternalStream(int(getattr(stream, "cuda_stream", stream)))
+    return torch.cuda.stream(stream)
+
+
+def _alloc_on_stream(fn):
+    """Runs an allocating convenience inside _on(its `stream` argument)."""
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def wrapper(*args, **kwargs):
+        with _on(sig.bind_partial(*args, **kwargs).arguments.get("stream")):
+            return fn(*args, **kwargs)
+    return wrapper
 
 
 def _ptr(t, dtype=None, name="tensor"):
@@ -353,6 +380,15 @@ def hvms_segmented_sort_pairs_i32(k_in, v_in, k_out, v_out, d_offsets, n_total, 
         int(n_total), int(max_seg), p, b, _stream(stream), _opts(opts)))
 
 
+def hvms_segmented_status(ws, status, stream=None):
+    """Enqueue the copy of the status words of the last segmented call on
+    workspace ws into status (int64 device tensor of at least 3 entries)."""
+    if status.numel() < 3:
+        raise ValueError("status needs 3 int64 entries")
+    _check("hvms_segmented_status", lib().hvms_segmented_status(
+        _ptr(ws, None, "ws"), _ptr(status, torch.int64, "status"), _stream(stream)))
+
+
 def hvms_cdf_forward(params, x, y, stream=None):
     _check("hvms_cdf_forward", lib().hvms_cdf_forward(
         _ptr(params, torch.float32), _ptr(x, torch.float32), _ptr(y, torch.float32), x.numel(),
@@ -397,6 +433,7 @@ def _auto(op, n, opts):
     return tune.tuned_options(op, n)
 
 
+@_alloc_on_stream
 def sort(keys, out=None, opts=None, stream=None):
     """Sorted copy of an int32 device tensor (out may be keys: in place)."""
     opts = _auto("sort", keys.numel(), opts)
@@ -407,6 +444,7 @@ def sort(keys, out=None, opts=None, stream=None):
     return out
 
 
+@_alloc_on_stream
 def sort_pairs(keys, vals, keys_out=None, vals_out=None, opts=None, stream=None):
     opts = _auto("sort_pairs", keys.numel(), opts)
     keys_out = torch.empty_like(keys) if keys_out is None else keys_out
@@ -420,6 +458,7 @@ _SORT64 = {torch.int64: hvms_sort_i64, torch.uint64: hvms_sort_u64,
            torch.float64: hvms_sort_f64}
 
 
+@_alloc_on_stream
 def sort_keys(keys, out=None, opts=None, stream=None):
     """Sorted copy of a device tensor of int32, uint32 (torch.uint32), float32
     (IEEE 754 totalOrder), int64, uint64 (torch.uint64) or float64 keys; out
@@ -445,6 +484,7 @@ def sort_keys(keys, out=None, opts=None, stream=None):
     return out
 
 
+@_alloc_on_stream
 def sort_pairs_keys(keys, vals, keys_out=None, vals_out=None, opts=None, stream=None):
     """sort_pairs for int32, uint32 (torch.uint32) or float32 keys with int32
     values, lexicographic (key, value)."""
@@ -461,6 +501,7 @@ def sort_pairs_keys(keys, vals, keys_out=None, vals_out=None, opts=None, stream=
     return keys_out, vals_out
 
 
+@_alloc_on_stream
 def sort_by_key(keys, vals, keys_out=None, vals_out=None, opts=None, stream=None):
     """Stable sort of int32 keys carrying 64-bit payloads (vals: any 8-byte
     dtype); equal keys keep their input order.  keys_out may be keys."""
@@ -473,12 +514,14 @@ def sort_by_key(keys, vals, keys_out=None, vals_out=None, opts=None, stream=None
     return keys_out, vals_out
 
 
+@_alloc_on_stream
 def sort_runs(keys, run_log2, out=None, opts=None, stream=None):
     out = torch.empty_like(keys) if out is None else out
     hvms_sort_runs_i32(keys, out, run_log2, stream, opts)
     return out
 
 
+@_alloc_on_stream
 def merge_pass(keys, run_len, out=None, opts=None, stream=None):
     out = torch.empty_like(keys) if out is None else out
     ws = _workspace(lib().hvms_merge_workspace_bytes(keys.numel(), int(run_len), _opts(opts)),
@@ -487,17 +530,33 @@ def merge_pass(keys, run_len, out=None, opts=None, stream=None):
     return out
 
 
+@_alloc_on_stream
 def corank(a, b, diag, opts=None, stream=None):
     out = torch.empty(diag.numel(), dtype=torch.int64, device=a.device)
     hvms_corank_i32(a, b, diag, out, stream, opts)
     return out
 
 
+def _host_offsets(offsets, n_keys):
+    """Offsets on the host, checked: nondecreasing, within [0, n_keys].  The
+    library skips invalid segments (and counts them, see
+    hvms_segmented_status); the conveniences refuse them instead."""
+    off_host = offsets.cpu()
+    if off_host.numel():
+        if off_host.dtype != torch.int64:
+            raise ValueError(f"offsets must be int64, got {off_host.dtype}")
+        if int(off_host[0]) < 0 or int(off_host[-1]) > n_keys or \
+                bool((off_host[1:] < off_host[:-1]).any()):
+            raise ValueError("offsets must be nondecreasing and within [0, number of keys]")
+    return off_host
+
+
+@_alloc_on_stream
 def segmented_sort(keys, offsets, max_seg=None, out=None, opts=None, stream=None):
     """offsets: int64 tensor of nseg+1 entries (host or device)."""
     opts = _auto("segmented", keys.numel(), opts)
     out = torch.empty_like(keys) if out is None else out
-    off_host = offsets.cpu()
+    off_host = _host_offsets(offsets, keys.numel())
     nseg = off_host.numel() - 1
     n_total = int(off_host[-1]) if nseg >= 0 and off_host.numel() else 0
     if max_seg is None:
@@ -509,10 +568,11 @@ def segmented_sort(keys, offsets, max_seg=None, out=None, opts=None, stream=None
     return out
 
 
+@_alloc_on_stream
 def segmented_sort_pairs(keys, vals, offsets, max_seg=None, opts=None, stream=None):
     opts = _auto("segmented_pairs", keys.numel(), opts)
     ko, vo = torch.empty_like(keys), torch.empty_like(vals)
-    off_host = offsets.cpu()
+    off_host = _host_offsets(offsets, keys.numel())
     nseg = off_host.numel() - 1
     n_total = int(off_host[-1]) if off_host.numel() else 0
     if max_seg is None:
@@ -551,6 +611,7 @@ def grouped_workspace_bytes(offsets, max_group_keys=1 << 30, opts=None):
                                                 _opts(opts if opts is not None else {}))
 
 
+@_alloc_on_stream
 def segmented_sort_pairs_grouped(keys, vals, offsets, max_group_keys=1 << 30, opts=None,
                                  stream=None, opts_for_group=None, ws=None):
     """In-place segmented pair sort with bounded scratch: the segments are
@@ -585,12 +646,14 @@ def segmented_sort_pairs_grouped(keys, vals, offsets, max_group_keys=1 << 30, op
     return keys, vals
 
 
+@_alloc_on_stream
 def cdf_forward(params, x, stream=None):
     y = torch.empty_like(x)
     hvms_cdf_forward(params, x, y, stream)
     return y
 
 
+@_alloc_on_stream
 def cdf_backward(params, x, t, stream=None):
     grad = torch.empty(CDF_PARAMS, dtype=torch.float32, device=x.device)
     loss = torch.empty(1, dtype=torch.float32, device=x.device)
@@ -604,12 +667,14 @@ def cdf_adam_step(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps
     hvms_cdf_adam_step(params, m, v, grad, step, lr, beta1, beta2, eps, stream)
 
 
+@_alloc_on_stream
 def cdf_sample(keys, m, seed=0, stream=None):
     out = torch.empty(int(m), dtype=torch.int32, device=keys.device)
     hvms_cdf_sample_i32(keys, m, seed, out, stream)
     return out
 
 
+@_alloc_on_stream
 def fit_cdf_model(keys, frac=0.01, steps=400, batch=65536, lr=1e-3, seed=0, init=None,
                   stream=None):
     """The learned part end to end on the device: draw frac * n keys, sort the
@@ -624,6 +689,7 @@ def fit_cdf_model(keys, frac=0.01, steps=400, batch=65536, lr=1e-3, seed=0, init
     return params
 
 
+@_alloc_on_stream
 def cdf_train(params, sorted_keys, batch=65536, steps=500, lr=1e-3, seed=0, stream=None):
     """Trains params (in place) on a sorted sample; returns (params, m, v)."""
     m = torch.zeros_like(params)

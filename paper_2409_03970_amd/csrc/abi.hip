@@ -554,7 +554,7 @@ int hvms_corank_i32(const int32_t *d_a, int64_t m, const int32_t *d_b, int64_t k
 int64_t hvms_segmented_workspace_bytes(int64_t n_total, int64_t nseg, int64_t max_seg,
                                        int32_t pairs, const hvms_options *opt)
 {
-    if (n_total < 0 || nseg < 0 || max_seg < 0)
+    if (n_total < 0 || nseg < 0)
         return HVMS_ERR_INVALID_ARG;
     Cfg c;
     const int st = resolve(opt, pairs != 0, c);
@@ -570,7 +570,7 @@ static int run_segmented(const int32_t *kin, const int32_t *vin, int32_t *kout, 
                          void *ws, size_t ws_bytes, void *stream, const hvms_options *opt)
 {
     const bool pairs = vin != nullptr;
-    if (nseg < 0 || n_total < 0 || max_seg < 0 || (nseg > 0 && !off) || nseg >= (1ll << 31))
+    if (nseg < 0 || n_total < 0 || (nseg > 0 && !off) || nseg >= (1ll << 31))
         return HVMS_ERR_INVALID_ARG;
     if (n_total > 0 && (!kin || !kout || (pairs && (!vin || !vout))))
         return HVMS_ERR_INVALID_ARG;
@@ -597,7 +597,11 @@ static int run_segmented(const int32_t *kin, const int32_t *vin, int32_t *kout, 
     a.off = off;
     a.nseg = nseg;
     a.n_total = n_total;
-    a.passes = max_seg > tile ? ilog2_exact((max_seg + tile - 1) / tile) : 0;
+    // a negative max_seg: no bound known, enqueue the passes a segment of
+    // all n_total keys would need (passes with no tiles cost a few empty
+    // launches)
+    const int64_t bound = max_seg < 0 ? n_total : max_seg;
+    a.passes = bound > tile ? ilog2_exact((bound + tile - 1) / tile) : 0;
     a.R = c.R;
     a.NT = c.NT;
     a.K = c.K;
@@ -611,6 +615,13 @@ static int run_segmented(const int32_t *kin, const int32_t *vin, int32_t *kout, 
     if (a.passes > 0 && n_total < 16)
         return HVMS_ERR_INVALID_ARG;
     return hip_status(launch_segmented(a, (hipStream_t)stream));
+}
+
+int hvms_segmented_status(const void *d_ws, int64_t *d_status, void *stream)
+{
+    if (!d_ws || !d_status || ((uintptr_t)d_ws & 255))
+        return HVMS_ERR_INVALID_ARG;
+    return hip_status(launch_seg_status(d_ws, d_status, (hipStream_t)stream));
 }
 
 int hvms_segmented_sort_i32(const int32_t *d_in, int32_t *d_out, const int64_t *d_offsets,

@@ -104,5 +104,7 @@ struct SegArgs {
 };
 bool segmented_supported(int R, int NT, bool pairs);
 hipError_t launch_segmented(const SegArgs &a, hipStream_t s);
+// the status words of the last segmented call on workspace ws
+hipError_t launch_seg_status(const void *ws, int64_t *out, hipStream_t s);
 
 }  // namespace hvms

@@ -44,6 +44,9 @@ enum : int {
     C_TASK = C_BASE + kMaxBuckets,  // first task of each bucket
     C_NTASK = C_TASK + kMaxBuckets, // total tasks
     C_TICKET,                       // task ticket counter
+    C_OVER,                         // segments with P_s above the enqueued passes
+    C_SKIP,                         // segments skipped: offsets outside [0, n_total] or decreasing
+    C_BAD,                          // 1: offsets inconsistent with n_total, nothing sorted
     C_LCNT = 80,                    // large segments with P_s == P
     C_TCNT = C_LCNT + kMaxP,        // merge tiles of those segments
     C_TCUR = C_TCNT + kMaxP,        // tile-list cursors per P
@@ -71,6 +74,7 @@ struct SegParams {
     int64_t nseg, n_total;
     int64_t max_pieces, max_tiles;  // list capacities in the workspace
     int tile_log2, r_log2, nb;  // nb = buckets = tile_log2 - r_log2 + 1
+    int passes;                 // merge passes enqueued by the host
     int64_t tm;
 };
 
@@ -88,19 +92,27 @@ __global__ void seg_init_kernel(unsigned long long *ctrl)
 
 __global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned long long *ctrl)
 {
-    __shared__ unsigned long long cnt[kMaxBuckets], lcnt[kMaxP], tcnt[kMaxP];
+    __shared__ unsigned long long cnt[kMaxBuckets], lcnt[kMaxP], tcnt[kMaxP], over, skip;
     for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
         lcnt[i] = 0;
         tcnt[i] = 0;
         if (i < kMaxBuckets)
             cnt[i] = 0;
     }
+    if (threadIdx.x == 0) {
+        over = 0;
+        skip = 0;
+    }
     __syncthreads();
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s < P.nseg) {
-        // a segment outside [0, n_total] is treated as empty
+        // a segment outside [0, n_total], or with decreasing offsets, is
+        // treated as empty and counted
         const int64_t a = P.off[s], e = P.off[s + 1];
-        const int64_t size = (a >= 0 && e <= P.n_total) ? e - a : 0;
+        const bool valid = a >= 0 && e <= P.n_total && e >= a;
+        const int64_t size = valid ? e - a : 0;
+        if (!valid)
+            atomicAdd(&skip, 1ull);
         if (size > 0) {
             const int64_t tile = (int64_t)1 << P.tile_log2;
             if (size <= tile) {
@@ -111,10 +123,18 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned lo
                 atomicAdd(&cnt[P.nb - 1], (unsigned long long)np);
                 atomicAdd(&lcnt[ps], 1ull);
                 atomicAdd(&tcnt[ps], (unsigned long long)((size + P.tm - 1) / P.tm));
+                if (ps > P.passes)
+                    atomicAdd(&over, 1ull);
             }
         }
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        if (over)
+            atomicAdd(&ctrl[C_OVER], over);
+        if (skip)
+            atomicAdd(&ctrl[C_SKIP], skip);
+    }
     for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
         if (lcnt[i])
             atomicAdd(&ctrl[C_LCNT + i], lcnt[i]);
@@ -135,9 +155,14 @@ __global__ void seg_plan_kernel(SegParams P, unsigned long long *ctrl)
     for (int p = 0; p < kMaxP; ++p)
         tiles_total += ctrl[C_TCNT + p];
     if (pieces > (unsigned long long)P.max_pieces || tiles_total > (unsigned long long)P.max_tiles) {
-        // inconsistent offsets / n_total: leave every task and pass empty
+        // inconsistent offsets / n_total: leave every task and pass empty,
+        // keep the counts of the status words and raise the flag
+        const unsigned long long over = ctrl[C_OVER], skip = ctrl[C_SKIP];
         for (int i = 0; i < C_WORDS; ++i)
             ctrl[i] = 0;
+        ctrl[C_OVER] = over;
+        ctrl[C_SKIP] = skip;
+        ctrl[C_BAD] = 1;
         return;
     }
     unsigned long long base = 0, task = 0;
@@ -182,7 +207,7 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
     if (s < P.nseg) {
         o = P.off[s];
         const int64_t e = P.off[s + 1];
-        size = (o >= 0 && e <= P.n_total) ? e - o : 0;
+        size = (o >= 0 && e <= P.n_total && e >= o) ? e - o : 0;
         if (size > 0) {
             if (size <= tile) {
                 b = bucket_of(P, size);
@@ -196,7 +221,10 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
             }
             mine = atomicAdd(&cnt[b], (unsigned long long)np);
         }
-        passes[s] = ps;
+        // a segment needing more passes than are enqueued runs the enqueued
+        // ones (and is counted in C_OVER): its pieces start where that pass
+        // count lands them in the output
+        passes[s] = ps < P.passes ? ps : P.passes;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
@@ -208,7 +236,7 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
     __syncthreads();
     if (b >= 0) {
         const int64_t first = bbase[b] + mine;
-        const int dst = (ps & 1) ? 1 : 0;
+        const int dst = ((ps < P.passes ? ps : P.passes) & 1) ? 1 : 0;
         for (int64_t i = 0; i < np && first + i < P.max_pieces; ++i) {
             Piece pc;
             pc.off = o + i * tile;
@@ -333,7 +361,23 @@ void seg_merge_kernel(SegMap map, int64_t run,
 
 int64_t a256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
+__global__ void seg_status_kernel(const unsigned long long *ctrl, int64_t *out)
+{
+    if (threadIdx.x == 0) {
+        out[0] = (int64_t)ctrl[C_OVER];
+        out[1] = (int64_t)ctrl[C_SKIP];
+        out[2] = (int64_t)ctrl[C_BAD];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_seg_status(const void *ws, int64_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(seg_status_kernel, dim3(1), dim3(64), 0, s,
+                       (const unsigned long long *)ws, out);
+    return hipGetLastError();
+}
 
 SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool pairs)
 {
@@ -447,6 +491,7 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
     P.tile_log2 = tile_log2;
     P.r_log2 = r_log2;
     P.nb = tile_log2 - r_log2 + 1;
+    P.passes = a.passes;
     P.tm = a.TM;
     char *ws = (char *)a.ws;
     unsigned long long *ctrl = (unsigned long long *)(ws + L.ctrl);

@@ -26,7 +26,7 @@ def _declared():
 
 def test_every_declared_symbol_is_exported():
     names = _declared()
-    assert len(names) == 29
+    assert len(names) >= 30
     L = hv.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -153,6 +153,28 @@ def test_segmented_workspace_and_errors():
                                      1 << 30, None, None) == -1
     assert L.hvms_segmented_sort_pairs_i32(FAKE, None, FAKE, FAKE, FAKE, 3, 100, 50, FAKE,
                                            1 << 30, None, None) == -1
+
+
+def test_segmented_status_and_unknown_bound():
+    L = hv.lib()
+    # a negative max_seg means "no bound known": accepted, same workspace
+    assert L.hvms_segmented_workspace_bytes(1 << 20, 100, -1, 0, None) == \
+        L.hvms_segmented_workspace_bytes(1 << 20, 100, 65536, 0, None)
+    # the status query rejects null and misaligned pointers on the host
+    assert L.hvms_segmented_status(None, FAKE, None) == -1
+    assert L.hvms_segmented_status(FAKE, None, None) == -1
+    assert L.hvms_segmented_status(ctypes.c_void_p(0x100010), FAKE, None) == -1
+
+
+def test_segmented_conveniences_refuse_invalid_offsets():
+    import torch
+    ok = hv._host_offsets(torch.tensor([0, 3, 3, 10], dtype=torch.int64), 10)
+    assert ok.tolist() == [0, 3, 3, 10]
+    for bad, n in (([0, 5, 4, 10], 10), ([-1, 5], 10), ([0, 11], 10)):
+        with pytest.raises(ValueError):
+            hv._host_offsets(torch.tensor(bad, dtype=torch.int64), n)
+    with pytest.raises(ValueError):
+        hv._host_offsets(torch.tensor([0, 5], dtype=torch.int32), 10)
 
 
 def test_cdf_argument_errors():

@@ -254,3 +254,101 @@ def test_all_permutations_of_8_as_segments():
     assert (ko == np.arange(8)).all()
     # value j of segment s is where key j stood: perms[s, vo[s, j]] == j
     assert (np.take_along_axis(perms, vo, axis=1) == np.arange(8)).all()
+
+
+# ------------------------------------------------ status words (max_seg, offsets)
+
+def _raw_segmented(k, offs, max_seg, opts, out=None, vals=None):
+    """One raw ABI call; returns (output keys, output values or None, status)."""
+    n = int(offs[-1]) if offs.numel() else 0
+    nseg = offs.numel() - 1
+    d_off = offs.to(DEV)
+    ws = torch.empty(max(hv.lib().hvms_segmented_workspace_bytes(n, nseg, max(max_seg, 0),
+                                                                   int(vals is not None),
+                                                                   hv._opts(opts)), 256),
+                     dtype=torch.uint8, device=DEV)
+    out = torch.empty_like(k) if out is None else out
+    if vals is None:
+        hv.hvms_segmented_sort_i32(k, out, d_off, n, max_seg, ws, opts=opts)
+        vo = None
+    else:
+        vo = torch.empty_like(vals)
+        hv.hvms_segmented_sort_pairs_i32(k, vals, out, vo, d_off, n, max_seg, ws, opts=opts)
+    st = torch.full((3,), -7, dtype=torch.int64, device=DEV)
+    hv.hvms_segmented_status(ws, st)
+    return out, vo, st.cpu().tolist()
+
+
+# block tile 2048 keys: a segment of s keys needs ceil(log2(ceil(s / 2048))) passes
+_SMALL = {"keys_per_lane": 8, "block_threads": 256}
+_SIZES = [5, 2048, 2049, 4096, 4097, 9000, 3 * 2048 + 7, 70000, 0, 131072, 1000]
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_max_seg_underestimated_reports_and_stays_a_permutation(pairs):
+    # max_seg = 4096 enqueues one pass: segments above 4096 keys are left as
+    # sorted runs of 4096 (an exact, checkable permutation) and counted
+    sizes = torch.tensor(_SIZES, dtype=torch.int64)
+    offs = inputs.offsets_from_sizes(sizes)
+    n = int(offs[-1])
+    k = inputs.keys(n, "uniform", seed=21, device=DEV)
+    v = torch.arange(n, dtype=torch.int32, device=DEV) if pairs else None
+    _say("max_seg underestimated, pairs", pairs)
+    out, vo, st = _raw_segmented(k, offs, 4096, _SMALL, vals=v)
+    over = int((sizes > 4096).sum())
+    assert st == [over, 0, 0]
+    kh, got = k.cpu().numpy(), out.cpu().numpy()
+    vh = v.cpu().numpy() if pairs else None
+    gotv = vo.cpu().numpy() if pairs else None
+    o = offs.tolist()
+    for s in range(len(_SIZES)):
+        run = 4096 if _SIZES[s] > 4096 else max(_SIZES[s], 1)
+        for a in range(o[s], o[s + 1], run):
+            b = min(a + run, o[s + 1])
+            if pairs:
+                ek, ev = oracle.sort_pairs(kh[a:b], vh[a:b])
+                assert np.array_equal(got[a:b], ek) and np.array_equal(gotv[a:b], ev), (s, a)
+            else:
+                assert np.array_equal(got[a:b], oracle.sort(kh[a:b])), (s, a)
+
+
+def test_max_seg_unknown_sorts_everything():
+    sizes = torch.tensor(_SIZES, dtype=torch.int64)
+    offs = inputs.offsets_from_sizes(sizes)
+    k = inputs.keys(int(offs[-1]), "zipf", seed=22, device=DEV)
+    out, _, st = _raw_segmented(k, offs, -1, _SMALL)
+    assert st == [0, 0, 0]
+    assert np.array_equal(out.cpu().numpy(),
+                          oracle.segmented_sort(k.cpu().numpy(), offs.numpy()))
+    # an exact bound gives the same output and a clean status
+    out2, _, st2 = _raw_segmented(k, offs, int(sizes.max()), _SMALL)
+    assert st2 == [0, 0, 0] and torch.equal(out, out2)
+
+
+def test_invalid_offsets_are_counted_and_skipped():
+    # segment 1 ends past n_total, segment 2 has decreasing offsets: both are
+    # skipped (their keys untouched) and counted; segment 0 is sorted
+    n = 3000
+    k = inputs.keys(n, "uniform", seed=23, device=DEV)
+    offs = torch.tensor([0, 1000, 4000, 3000], dtype=torch.int64)
+    pre = torch.full((n,), -5, dtype=torch.int32, device=DEV)
+    out, _, st = _raw_segmented(k, offs, -1, _SMALL, out=pre)
+    assert st == [0, 2, 0]
+    got = out.cpu().numpy()
+    assert np.array_equal(got[:1000], oracle.sort(k.cpu().numpy()[:1000]))
+    assert (got[1000:] == -5).all()
+
+
+def test_inconsistent_offsets_flagged_and_nothing_written():
+    # offsets 0, n, 0, n, ...: four segments each spanning [0, n) (and three
+    # decreasing ones between them, skipped).  Their sizes add up to four
+    # times n_total, more pieces than the workspace plans for n_total keys,
+    # so the call sorts and writes nothing and raises status word 2.
+    n = 20 * 2048
+    k = inputs.keys(n, "uniform", seed=24, device=DEV)
+    offs = torch.tensor([0, n] * 3 + [0, n][:1] + [n], dtype=torch.int64)
+    assert offs.tolist() == [0, n, 0, n, 0, n, 0, n]
+    pre = torch.full((n,), -9, dtype=torch.int32, device=DEV)
+    out, _, st = _raw_segmented(k, offs, n, _SMALL, out=pre)
+    assert st == [0, 3, 1]
+    assert bool((out == -9).all())
