@@ -79,21 +79,69 @@ def make_events(k):
     return ev
 
 
-def cpu_baseline(dists, log2n, seed=0, sample_log2=24):
-    """The oracle (single thread, as written) on the first 2^sample_log2 keys
-    of each distribution's input."""
+def _host_cpu():
+    """Host CPU model name and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, usable, os.cpu_count()
+
+
+def cpu_baseline(dists, log2n, seed=0):
+    """The oracle as written (a single-threaded merge sort) on the full
+    headline inputs: one sort of each distribution's 2^log2n keys, the six
+    sorts running at once on six host threads, so the measured rate is the
+    host's six-core rate for this workload.  Beside it: the per-sort
+    single-thread rate, the 2^20-key uniform input (five sorts, one thread),
+    and the C++ library's std::sort on the same full inputs (context)."""
+    import concurrent.futures
     import oracle
-    total_keys, total_s = 0, 0.0
-    for d in dists:
-        x = inputs.keys(1 << min(sample_log2, log2n), d, seed=seed, device="cpu").numpy()
+    dev = torch.device("cuda", 0)
+    xs = [inputs.keys(1 << log2n, d, seed=seed, device=dev).cpu().numpy() for d in dists]
+    torch.cuda.empty_cache()
+
+    def timed(fn, x):
         t0 = time.perf_counter()
-        oracle.sort(x)
-        total_s += time.perf_counter() - t0
-        total_keys += x.size
-    return {"value": total_keys / total_s, "unit": "keys/s", "cores": 1, "kind": "oracle",
-            "sample": f"first 2^{min(sample_log2, log2n)} keys of each of the {len(dists)} "
-                      f"inputs ({', '.join(dists)}), sorted once each by the single-threaded "
-                      f"oracle merge sort; {total_s:.1f} s of CPU time"}
+        fn(x)
+        return time.perf_counter() - t0
+
+    def concurrent_run(fn):
+        with concurrent.futures.ThreadPoolExecutor(len(xs)) as ex:
+            w0 = time.perf_counter()
+            per = list(ex.map(lambda x: timed(fn, x), xs))
+            return time.perf_counter() - w0, per
+
+    oracle.lib()
+    oracle.std_sort(xs[0][:16])                     # load both libraries first
+    wall, per = concurrent_run(oracle.sort)
+    n_all = sum(x.size for x in xs)
+    small = inputs.keys(1 << 20, "uniform", seed=seed, device=dev).cpu().numpy()
+    t_small = [timed(oracle.sort, small) for _ in range(5)]
+    std_wall, std_per = concurrent_run(oracle.std_sort)
+    model, usable, total = _host_cpu()
+    return {"value": n_all / wall, "unit": "keys/s", "cores": len(xs), "kind": "oracle",
+            "sample": f"the full headline workload: one sort of each of the {len(xs)} inputs of "
+                      f"2^{log2n} keys ({', '.join(dists)}) by the single-threaded oracle merge "
+                      f"sort, the {len(xs)} sorts at once on {len(xs)} host threads; "
+                      f"{wall:.1f} s wall",
+            "per_sort_single_thread_keys_per_s": round(n_all / sum(per), 1),
+            "per_distribution_s": {d: round(t, 2) for d, t in zip(dists, per)},
+            "uniform_2p20_single_thread_keys_per_s": round(small.size / float(np.median(t_small)), 1),
+            "uniform_2p20_s": [round(t, 4) for t in t_small],
+            "context_std_sort": {"value": n_all / std_wall, "unit": "keys/s", "cores": len(xs),
+                                 "per_sort_single_thread_keys_per_s": round(n_all / sum(std_per), 1),
+                                 "wall_s": round(std_wall, 2)},
+            "host_cpu_model": model, "host_cores_usable": usable, "host_cores_total": total}
 
 
 def merge_passes(n, tile, ways=2):
@@ -224,6 +272,35 @@ def merge_table3_bench(n):
     return res
 
 
+_M64 = (1 << 64) - 1
+
+
+def _s64(c):
+    """A 64-bit constant as the signed value torch's int64 holds."""
+    return c - (1 << 64) if c >= 1 << 63 else c
+
+
+def gpu_multiset_hash(t, chunk=1 << 26):
+    """Sum over the keys of a 64-bit mix of each key (SplitMix64's output
+    function), modulo 2^64, on the device: equal for any two arrangements of
+    one multiset, different with probability about 2^-64 otherwise.  A
+    certificate that a sort output is a permutation of its input."""
+    total = torch.zeros((), dtype=torch.int64, device=t.device)
+    for a in range(0, t.numel(), chunk):
+        z = t[a:a + chunk].to(torch.int64) & 0xFFFFFFFF
+        z = z + _s64(0x9E3779B97F4A7C15)
+        z = (z ^ ((z >> 30) & ((1 << 34) - 1))) * _s64(0xBF58476D1CE4E5B9)
+        z = (z ^ ((z >> 27) & ((1 << 37) - 1))) * _s64(0x94D049BB133111EB)
+        z = z ^ ((z >> 31) & ((1 << 33) - 1))
+        total += z.sum()
+    return int(total.item()) & _M64
+
+
+def sort_certificate(x, y):
+    """y is nondecreasing and a permutation of x (multiset hash)."""
+    return bool((y[1:] >= y[:-1]).all()) and gpu_multiset_hash(x) == gpu_multiset_hash(y)
+
+
 def _median_ms(fn, reps=3):
     fn()
     torch.cuda.synchronize()
@@ -330,7 +407,22 @@ def by_key_bench(n):
             "certificate_ok": ok}
 
 
-def batched_bench():
+def sort_dist_bench(dist, reps=5, log2n=28):
+    """2^log2n keys of one distribution, the tuned options, `reps` timed sorts
+    (a short run for kernel traces and counters of one input)."""
+    dev = torch.device("cuda", 0)
+    n = 1 << log2n
+    x = inputs.keys(n, dist, seed=0, device=dev)
+    out = torch.empty_like(x)
+    from paper_2409_03970_amd import tune
+    opts = tune.tuned_options("sort", n) or {}
+    ws = hv._workspace(hv.lib().hvms_sort_workspace_bytes(n, 0, hv._opts(opts)), dev)
+    ms = _median_ms(lambda: hv.hvms_sort_i32(x, out, ws, opts=opts), reps=reps)
+    return {"dist": dist, "n": n, "ms": round(ms, 3), "gkeys_per_s": round(n / ms / 1e6, 2),
+            "options": opts, "certified": sort_certificate(x, out)}
+
+
+def batched_bench(per_array=True):
     """200,000 arrays, sizes log-uniform in [1, 65536]: one batched call
     (eager and as a replayed HIP graph) against one plain sort per array."""
     dev = torch.device("cuda", 0)
@@ -357,6 +449,10 @@ def batched_bench():
     torch.cuda.current_stream().wait_stream(s)
     graph_ms = _median_ms(g.replay)
     graph_ok = bool(torch.equal(out, ref))
+    if not per_array:
+        return {"keys": n, "segments": int(sizes.numel()), "options": opts,
+                "batched_ms": round(eager_ms, 3), "graph_ms": round(graph_ms, 3),
+                "graph_replay_equal": graph_ok}
     # plain sort per array, same inputs, one ABI call each (workspace sized once)
     ws2 = hv._workspace(hv.lib().hvms_sort_workspace_bytes(max_seg, 0, None), dev)
     L = hv.lib()
@@ -403,11 +499,20 @@ def learned_bench():
     t1.record()
     torch.cuda.synchronize()
     res = {"n": n, "train_ms_incl_sample_sort": round(t0.elapsed_time(t1), 2)}
+    ref = None
     for name, mode in (("binary", hv.CORANK_BINARY), ("learned", hv.CORANK_LEARNED),
                        ("linear", hv.CORANK_LINEAR)):
         res[name] = _mode_stats(x, out, ws, opts, params, mode, radius=13)
-    o = out[:: 1 << 10]
-    res["sorted_ok"] = bool((out[1:] >= out[:-1]).all()) and o.numel() > 0
+        # each mode's output as it is produced: the binary one certified
+        # (nondecreasing, a permutation of the input), the others identical
+        if ref is None:
+            res[name]["output_certified"] = sort_certificate(x, out)
+            ref = out.clone()
+        else:
+            res[name]["output_equals_binary"] = bool(torch.equal(out, ref))
+    res["sorted_ok"] = bool(res["binary"]["output_certified"] and
+                            res["learned"]["output_equals_binary"] and
+                            res["linear"]["output_equals_binary"])
     return res
 
 
@@ -617,6 +722,15 @@ def measure(opts, xs, dists, out, steps, warmup):
     }
 
 
+# single measurements for traces and counters (--only)
+ONLY = {
+    "learned_2p30_mixture": lambda: learned_bench(),
+    "sort_2p28_uniform": lambda: sort_dist_bench("uniform"),
+    "sort_2p28_sorted": lambda: sort_dist_bench("sorted"),
+    "batched_200k_segments": lambda: batched_bench(per_array=False),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -626,8 +740,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--all", action="store_true",
-                    help="also the 50,000-segment key-value batch (about 2.2e10 pairs, "
-                         "a minute or two)")
+                    help="accepted for compatibility: every extra runs by default")
     ap.add_argument("--profile-copy", action="store_true",
                     help="also copy one input once with torch (a plain copy of known size "
                          "that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -635,9 +748,9 @@ def main():
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--merge-tile", type=int, default=0)
     ap.add_argument("--wave-levels", type=int, default=0, help="levels + 1; 0 = default")
-    ap.add_argument("--only", choices=("learned_2p30_mixture",),
+    ap.add_argument("--only", choices=sorted(ONLY),
                     help="diagnostic: run just this measurement (no headline) and print "
-                         "its record; used by the co-rank counter profiles")
+                         "its record; used by the kernel traces and counter profiles")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -651,7 +764,7 @@ def main():
             torch.empty_like(a).copy_(a)
             torch.cuda.synchronize()
             del a
-        rec = {"only": args.only, **learned_bench()}
+        rec = {"only": args.only, **ONLY[args.only]()}
         print(json.dumps(rec), flush=True)
         return
 
@@ -698,6 +811,9 @@ def main():
             "merge_variant": opts.get("merge_variant") or 2, "merge_passes": passes,
             "merge_ways": opts.get("merge_ways") or 2,
             "parallelism": "single GPU",
+            # the headline mean includes the presorted inputs, whose tiles are
+            # copied rather than merged: the rate of each input beside it
+            "gkeys_per_s_by_distribution": per_dist,
         },
         "roofline": {
             "kernel": ("merge4_pipe_kernel (four-way merge pass: two merge levels per launch)"
@@ -774,7 +890,7 @@ def main():
                   ("merge_table3", lambda: merge_table3_bench(n)),
                   ("pairs_2p28", lambda: pairs_bench(n)),
                   ("sort_by_key_p64_2p28", lambda: by_key_bench(n)),
-                  ("batched_learned_pairs_50k_segments", config5_bench if args.all else None),
+                  ("batched_learned_pairs_50k_segments", config5_bench),
                   ("batched_200k_segments", batched_bench),
                   ("learned_2p30_mixture", learned_bench),
                   ("small_2p20", small_bench))

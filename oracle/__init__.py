@@ -21,12 +21,39 @@ _i32p = ctypes.POINTER(ctypes.c_int32)
 _i64p = ctypes.POINTER(ctypes.c_int64)
 
 
+_CTX_SRC = os.path.join(_HERE, "std_sort.cpp")
+_CTX_SO = os.path.join(_HERE, "libstdsort.so")
+_ctx = None
+
+
 def build():
-    """Compile oracle.c with gcc (always, so edits are picked up)."""
+    """Compile oracle.c with gcc (always, so edits are picked up), and the
+    std::sort context routine with g++."""
     tmp = _SO + ".tmp"
     subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
                     _SRC, "-o", tmp], check=True)
     os.replace(tmp, _SO)
+    tmp = _CTX_SO + ".tmp"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-Wall", "-fPIC", "-shared",
+                    _CTX_SRC, "-o", tmp], check=True)
+    os.replace(tmp, _CTX_SO)
+
+
+def std_sort(keys):
+    """Context only: a copy of int32 keys sorted by the C++ library's
+    std::sort (single thread).  Not an oracle: used to time the oracle against
+    a common library sort on the same host."""
+    global _ctx
+    if _ctx is None:
+        if not os.path.exists(_CTX_SO) or os.path.getmtime(_CTX_SO) < os.path.getmtime(_CTX_SRC):
+            build()
+        L = ctypes.CDLL(_CTX_SO)
+        L.context_std_sort_i32.argtypes = [_i32p, ctypes.c_int64]
+        L.context_std_sort_i32.restype = None
+        _ctx = L
+    a, p = _i32(np.array(keys, dtype=np.int32, copy=True))
+    _ctx.context_std_sort_i32(p, a.size)
+    return a
 
 
 def lib():

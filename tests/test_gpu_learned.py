@@ -160,6 +160,33 @@ def test_learned_sort_is_exact(dist):
         assert int(st[0]) > 0
 
 
+def test_full_size_2pow30_learned():
+    # the learned co-rank's own configuration: 2^30 mixture keys, the CDF
+    # model trained on the GPU from a 1 % sample, learned co-ranks with the
+    # bounded search (radius 2^13) in the tuned launch shape, element by
+    # element against the oracle (run in parts on the host); the linear and
+    # binary modes must give the identical array
+    import oracle_parts
+    from paper_2409_03970_amd import tune
+    n = 1 << 30
+    print("full size 2^30 learned", flush=True)
+    x = inputs.keys(n, "mixture", seed=0, device=DEV)
+    params = hv.fit_cdf_model(x, frac=0.01, steps=400, batch=65536, lr=3e-3, seed=2)
+    opts = dict(tune.tuned_options("sort", n) or {})
+    st = torch.zeros(hv.STATS_WORDS, dtype=torch.int64, device=DEV)
+    y = hv.sort(x, opts=dict(opts, corank_mode=hv.CORANK_LEARNED, cdf_params=params,
+                             radius_log2=13, stats=st))
+    torch.cuda.synchronize()
+    s = hv.corank_stats(st.cpu())
+    assert s["coranks"] > 0 and s.get("predicted", 0) > 0
+    want = oracle_parts.sort_in_parts(x.cpu().numpy(), parts=16, threads=16)
+    assert np.array_equal(y.cpu().numpy(), want)
+    for mode in (hv.CORANK_LINEAR, hv.CORANK_BINARY):
+        y2 = hv.sort(x, opts=dict(opts, corank_mode=mode, cdf_params=params, radius_log2=13))
+        assert torch.equal(y2, y), mode
+        del y2
+
+
 def test_learned_prediction_exact_on_disjoint_runs():
     # already sorted input: every pair of runs has disjoint key ranges, so the
     # model's breakpoints give every co-rank exactly (no fallback), while the

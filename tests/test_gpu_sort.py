@@ -5,6 +5,7 @@ import pytest
 import torch
 
 import oracle
+import oracle_parts
 import paper_2409_03970_amd as hv
 from paper_2409_03970_amd import inputs
 
@@ -277,15 +278,38 @@ def _full_check(x, y):
         assert lt <= p < le, p
 
 
+_EXPECTED = {}
+
+
+def expected_2p28(dist, seed=0):
+    """(input on the host, oracle's sorted array) of the 2^28-key benchmark
+    input of one distribution; kept for the tests that sort the same input."""
+    key = (dist, seed)
+    if key not in _EXPECTED:
+        _EXPECTED.clear()
+        xs = inputs.keys(1 << 28, dist, seed=seed, device=DEV).cpu().numpy()
+        _EXPECTED[key] = (xs, oracle_parts.sort_in_parts(xs, parts=16, threads=16))
+    return _EXPECTED[key]
+
+
 @pytest.mark.parametrize("dist", inputs.DISTRIBUTIONS)
 def test_full_size_2pow28(dist):
-    # the benchmark's workload and launch configuration: 2^28 keys
+    # the benchmark's workload in its launch configuration (the tuned
+    # options for 2^28 keys: four-way passes, seven merge launches over
+    # runs up to 2^27), compared element by element with the oracle
     n = 1 << 28
     _say("full size", dist)
-    x = inputs.keys(n, dist, seed=0, device=DEV)
+    xs, want = expected_2p28(dist)
+    x = torch.from_numpy(xs).to(DEV)
     y = hv.sort(x)
     torch.cuda.synchronize()
-    _full_check(x, y)
+    assert np.array_equal(y.cpu().numpy(), want)
+    if dist == "uniform":    # the same input, two-way passes (the best two-way shape)
+        from paper_2409_03970_amd import tune
+        o2 = tune.tuned_options("sort", n, two_way=True)
+        if o2:
+            y = hv.sort(x, opts=o2)
+            assert np.array_equal(y.cpu().numpy(), want)
 
 
 @pytest.mark.parametrize("ways", [2, 4])
@@ -411,3 +435,26 @@ def test_presorted_pairs_and_other_key_types(descending):
     d = d[::-1].copy() if descending else d
     yd = hv.sort_keys(torch.from_numpy(d).to(DEV))          # full tiles read packed
     assert np.array_equal(yd.cpu().numpy().view(np.uint64), oracle.sort_f64(d).view(np.uint64))
+
+
+# ----------------------------------------------- conveniences on a side stream
+
+def test_sort_on_side_stream_while_current_stream_allocates():
+    # the convenience wrappers allocate their workspace for the stream the
+    # kernels run on: memory freed when the call returns must not be handed
+    # to work on the current stream while the side stream still sorts
+    n = 1 << 24
+    x = inputs.keys(n, "uniform", seed=77, device=DEV)
+    want = oracle.sort(x.cpu().numpy())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for rep in range(3):
+        y = hv.sort(x, stream=side)
+        yk, yv = hv.sort_pairs(x, x, stream=side)
+        # the current stream reuses whatever the allocator hands out, at once
+        junk = [torch.full((n + 1024,), -1, dtype=torch.int32, device=DEV) for _ in range(6)]
+        side.synchronize()
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy(), want), rep
+        assert np.array_equal(yk.cpu().numpy(), want), rep
+        del junk, y, yk, yv

@@ -275,3 +275,22 @@ def test_32_wire_checker_on_small_wire_count_is_consistent():
     net = _bitonic_by_definition(4)
     assert oracle.network_failures01(net, 4) == 0
     assert oracle.network_failures01(net, 6) > 0
+
+
+def test_sort_in_parts_equals_oracle_sort():
+    # the identity the full-size GPU tests use to run the oracle on several
+    # host threads: sorting pieces and merging them gives oracle.sort's array
+    import oracle_parts
+    rng = np.random.default_rng(11)
+    for n, parts in ((1 << 20, 8), (100003, 5), (17, 4), (1, 3), (0, 2)):
+        for x in (rng.integers(-2**31, 2**31, n, dtype=np.int64).astype(np.int32),
+                  rng.integers(0, 7, n).astype(np.int32)):
+            assert np.array_equal(oracle_parts.sort_in_parts(x, parts), oracle.sort(x))
+
+
+def test_std_sort_context_routine_sorts():
+    # the library sort timed beside the oracle in the CPU baseline (context)
+    rng = np.random.default_rng(12)
+    for x in (rng.integers(-2**31, 2**31, 65537, dtype=np.int64).astype(np.int32),
+              np.zeros(0, np.int32), np.full(9, 3, np.int32)):
+        assert np.array_equal(oracle.std_sort(x), np.sort(x))
