@@ -40,7 +40,8 @@ enum {
     HVMS_ERR_INVALID_ARG = -1, /* null pointer with n > 0, n < 0, bad option   */
     HVMS_ERR_WORKSPACE = -2,   /* workspace null, too small or misaligned      */
     HVMS_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed   */
-    HVMS_ERR_UNSUPPORTED = -4  /* a tuning value the build has no kernel for   */
+    HVMS_ERR_UNSUPPORTED = -4, /* a tuning value the build has no kernel for   */
+    HVMS_ERR_TOO_LARGE = -5    /* input beyond a fixed-size entry point's limit */
 };
 
 /* Co-rank search modes for the global merge passes. */
@@ -140,6 +141,28 @@ int64_t hvms_sort_workspace_bytes(int64_t n, int32_t pairs, const hvms_options *
  */
 int hvms_sort_i32(const int32_t *d_in, int32_t *d_out, int64_t n, void *d_ws,
                   size_t ws_bytes, void *stream, const hvms_options *opt);
+
+/*
+ * hvms_sort_i32 without a workspace, for callers that cannot allocate device
+ * memory (code being captured into a HIP graph, serving loops, harnesses that
+ * forbid allocation).  Same arguments, result and errors as hvms_sort_i32,
+ * minus d_ws / ws_bytes: the scratch lives in one fixed device array of the
+ * library (HVMS_SORT_NOALLOC_SCRATCH_BYTES, held on every GPU the library
+ * runs on until the process ends).  The call allocates nothing and calls no
+ * allocating library routine; the first call on a device looks up that
+ * device's copy of the array (hipGetSymbolAddress, not a stream operation).
+ *   n            0 <= n <= HVMS_SORT_NOALLOC_MAX_KEYS; a larger n, or options
+ *                whose scratch exceeds the array, return HVMS_ERR_TOO_LARGE
+ *                before anything is enqueued.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (other streams, other host threads) race and corrupt each
+ * other; serialise them, e.g. on one stream.  The array keeps whatever the
+ * last call left; the sort needs nothing in it cleared.
+ */
+#define HVMS_SORT_NOALLOC_MAX_KEYS (1 << 22)
+#define HVMS_SORT_NOALLOC_SCRATCH_BYTES (17u << 20)
+int hvms_sort_i32_noalloc(const int32_t *d_in, int32_t *d_out, int64_t n, void *stream,
+                          const hvms_options *opt);
 
 /*
  * Sort n (key, value) pairs: the same merge sort (Sec. 2.1-2.4) with each

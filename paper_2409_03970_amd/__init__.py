@@ -27,6 +27,7 @@ __all__ = [
     "segment_groups", "grouped_workspace_bytes", "hvms_sort_u32", "hvms_sort_f32", "hvms_sort_pairs_u32",
     "hvms_sort_pairs_f32", "sort_keys", "sort_pairs_keys", "hvms_sort_i64", "hvms_sort_u64",
     "hvms_sort_f64", "hvms_sort_by_key_i32_p64", "sort_by_key", "hvms_segmented_status",
+    "hvms_sort_i32_noalloc", "SORT_NOALLOC_MAX_KEYS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -141,7 +142,10 @@ _SIGS = {
     "hvms_cdf_train": ([_vp, _vp, _vp, _vp, _i64, _i64, _i32, _f32, _u64, _vp, _sz, _vp], _i32),
     "hvms_cdf_sample_i32": ([_vp, _i64, _i64, _u64, _vp, _vp], _i32),
     "hvms_segmented_status": ([_vp, _vp, _vp], _i32),
+    "hvms_sort_i32_noalloc": ([_vp, _vp, _i64, _vp, _opt], _i32),
 }
+
+SORT_NOALLOC_MAX_KEYS = 1 << 22
 
 _lib = None
 
@@ -259,6 +263,17 @@ def hvms_sort_i32(d_in, d_out, ws=None, stream=None, opts=None):
     p, b = _wsargs(ws)
     _check("hvms_sort_i32", lib().hvms_sort_i32(
         _ptr(d_in, torch.int32, "in"), _ptr(d_out, torch.int32, "out"), d_in.numel(), p, b,
+        _stream(stream), _opts(opts)))
+
+
+def hvms_sort_i32_noalloc(d_in, d_out, stream=None, opts=None):
+    """hvms_sort_i32 on the library's fixed per-device scratch (no workspace,
+    no allocation; n <= SORT_NOALLOC_MAX_KEYS; calls overlapping on one GPU
+    race)."""
+    if d_in.numel() != d_out.numel():
+        raise ValueError("in and out differ in length")
+    _check("hvms_sort_i32_noalloc", lib().hvms_sort_i32_noalloc(
+        _ptr(d_in, torch.int32, "in"), _ptr(d_out, torch.int32, "out"), d_in.numel(),
         _stream(stream), _opts(opts)))
 
 

@@ -3,6 +3,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "hvms.h"
 #include "hvms_internal.h"
 
@@ -232,6 +234,7 @@ const char *hvms_status_string(int status)
     case HVMS_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
     case HVMS_ERR_HIP: return "HIP runtime error";
     case HVMS_ERR_UNSUPPORTED: return "unsupported tuning value";
+    case HVMS_ERR_TOO_LARGE: return "input larger than the fixed scratch of this entry point";
     default: return "unknown status";
     }
 }
@@ -264,6 +267,71 @@ int hvms_sort_i32(const int32_t *d_in, int32_t *d_out, int64_t n, void *d_ws, si
     if (st)
         return st;
     return run_sort(false, d_in, nullptr, d_out, nullptr, n, d_ws, (hipStream_t)stream, c);
+}
+
+}  // extern "C"
+
+// Scratch of hvms_sort_i32_noalloc: one fixed array per device.  In host
+// code its name stands for a host-side shadow, never the device address, so
+// every use below goes through the address hipGetSymbolAddress returns for
+// the current device.
+static __device__ __align__(256) unsigned char scratch[HVMS_SORT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64];  // per device, filled on its first call
+
+// this device's copy of the array, looked up once per device
+int scratch_for_current_device(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_status(e);
+    if (dev < 0 || dev >= 64)
+        return HVMS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_status(e);
+        if (!p || ((uintptr_t)p & 255))
+            return HVMS_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HVMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hvms_sort_i32_noalloc(const int32_t *d_in, int32_t *d_out, int64_t n, void *stream,
+                          const hvms_options *opt)
+{
+    if (n < 0 || (n > 0 && (!d_in || !d_out)))
+        return HVMS_ERR_INVALID_ARG;
+    Cfg c;
+    int st = resolve(opt, false, c);
+    if (st)
+        return st;
+    if (n > HVMS_SORT_NOALLOC_MAX_KEYS)
+        return HVMS_ERR_TOO_LARGE;
+    if (n == 0)
+        return HVMS_OK;
+    const int64_t need = sort_ws_layout(n, false, c).total;
+    if (need > (int64_t)HVMS_SORT_NOALLOC_SCRATCH_BYTES)
+        return HVMS_ERR_TOO_LARGE;
+    void *ws = nullptr;
+    if (need > 0) {
+        st = scratch_for_current_device(&ws);
+        if (st)
+            return st;
+    }
+    return run_sort(false, d_in, nullptr, d_out, nullptr, n, ws, (hipStream_t)stream, c);
 }
 
 int hvms_sort_pairs_i32(const int32_t *d_keys_in, const int32_t *d_vals_in, int32_t *d_keys_out,

@@ -177,6 +177,19 @@ def test_segmented_conveniences_refuse_invalid_offsets():
         hv._host_offsets(torch.tensor([0, 5], dtype=torch.int32), 10)
 
 
+def test_sort_noalloc_argument_errors():
+    # host-side checks of the allocation-free sort, before any GPU call
+    L = hv.lib()
+    assert L.hvms_sort_i32_noalloc(None, None, 0, None, None) == 0
+    assert L.hvms_sort_i32_noalloc(FAKE, FAKE, -1, None, None) == -1
+    assert L.hvms_sort_i32_noalloc(None, FAKE, 5, None, None) == -1
+    assert L.hvms_sort_i32_noalloc(FAKE, FAKE, hv.SORT_NOALLOC_MAX_KEYS + 1, None, None) == -5
+    assert L.hvms_status_string(-5).decode().startswith("input larger")
+    assert hv.SORT_NOALLOC_MAX_KEYS == 1 << 22
+    text = open(HEADER).read()
+    assert "#define HVMS_SORT_NOALLOC_MAX_KEYS (1 << 22)" in text
+
+
 def test_cdf_argument_errors():
     L = hv.lib()
     assert L.hvms_cdf_forward(FAKE, FAKE, FAKE, 0, None) == 0
