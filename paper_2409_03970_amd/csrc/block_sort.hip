@@ -131,7 +131,7 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
                 g < n ? map_elem(load_elem<T, PI, IO>(kin, vin, g), xin) : Traits<T>::kMax;
         }
         __syncthreads();
-        const LdsSkew<T> W{S, wave * (64 * R) + lane * R};
+        const LdsSkew<T> W{S, wave * (64 * R) + logical_lane(lane) * R};
 #pragma unroll
         for (int r = 0; r < R; ++r)
             v[r] = W[r];

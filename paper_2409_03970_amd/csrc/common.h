@@ -143,34 +143,22 @@ __device__ __forceinline__ int lane_id()
     return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
 
-// Value of v held by lane (lane ^ M).  DPP within a 16-lane row where a
-// control exists (quad permutes, row mirrors, row rotate by 8), ds_swizzle
-// (bit-mask mode, inside 32 lanes) for xor 4, 16 and 31, and ds_bpermute for
-// the partners across the two 32-lane halves.
+// Value of v held by lane (lane ^ M), for the partners the merge levels
+// reach this way: DPP quad permutes (xor 1, 2) and row rotate by 8 (xor 8
+// inside a 16-lane row), ds_swizzle in bit-mask mode for xor 4.  (xor 16
+// and 32 go through lane_swap below.)
 template <int M> __device__ __forceinline__ int32_t xlane32(int32_t v)
 {
-    // update_dpp with every row and bank enabled and bound_ctrl set, so the
-    // compiler can fold the exchange into the consuming v_min / v_max
+    static_assert(M == 1 || M == 2 || M == 4 || M == 8, "no single-operation exchange");
+    // update_dpp with every row and bank enabled and bound_ctrl set
     if constexpr (M == 1)
         return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);  // quad_perm 1,0,3,2
     else if constexpr (M == 2)
         return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);  // quad_perm 2,3,0,1
-    else if constexpr (M == 3)
-        return __builtin_amdgcn_update_dpp(0, v, 0x1B, 0xF, 0xF, true);  // quad_perm 3,2,1,0
     else if constexpr (M == 4)
         return __builtin_amdgcn_ds_swizzle(v, 0x101F);                    // xor 4
-    else if constexpr (M == 7)
-        return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true); // row_half_mirror
-    else if constexpr (M == 8)
-        return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, true); // row_ror:8
-    else if constexpr (M == 15)
-        return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true); // row_mirror
-    else if constexpr (M == 16)
-        return __builtin_amdgcn_ds_swizzle(v, 0x401F);              // xor 16
-    else if constexpr (M == 31)
-        return __builtin_amdgcn_ds_swizzle(v, 0x7C1F);              // xor 31
     else
-        return __builtin_amdgcn_ds_bpermute((lane_id() ^ M) << 2, v);
+        return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, true); // row_ror:8
 }
 
 template <int M, typename T> __device__ __forceinline__ T xlane(T v)
@@ -222,76 +210,184 @@ template <int R, typename T, int NET = 0> __device__ __forceinline__ void column
 
 // ------------------------------------- cross-lane bitonic merge levels (a3)
 //
-// Layout: lane l holds elements R*l .. R*l + R-1 of the wavefront's tile in
-// v[0..R).  Merge level K turns sorted runs of R*2^(K-1) (2^(K-1) adjacent
-// lanes) into runs of R*2^K.  In the all-ascending form of the bitonic
-// merger, element e first meets e ^ (R*2^K - 1): lane l ^ (2^K - 1), register
-// R-1-r (the "flip").  Then half-cleaners at distances R*2^(K-2) .. R run
-// across lanes (partner lane l ^ 2^j, same register), and the ones at R/2 ..
-// 1 run inside the lane.  The in-lane part is the serial part of the hybrid
-// merger of Sec. 2.4, the cross-lane part its vectorised part.
+// Layout: logical lane l holds elements R*l .. R*l + R-1 of the wavefront's
+// tile in v[0..R).  Merge level K turns sorted runs of R*2^(K-1) (2^(K-1)
+// adjacent logical lanes) into runs of R*2^K.  The runs alternate in
+// direction, as in Batcher's bitonic sort: level K leaves the run of logical
+// lanes with bit K set in descending order (ascending at the last level), so
+// the two runs level K merges form a bitonic sequence and every stage is a
+// half-cleaner.  Level 1 merges the ascending columns of the column sort
+// instead, and starts with the flip stage (element e against e ^ (2R - 1):
+// lane l ^ 1, register R-1-r).  The cross-lane half-cleaners (partner lane
+// l ^ 2^j, same register) are the vector part of the hybrid merger of Sec.
+// 2.4; the in-lane ones at distances R/2 .. 1 its serial part.
+//
+// Logical lane bits 0..5 sit at physical lane bits 0, 1, 3, 4, 5, 2.  The
+// partners of the five most used bits are then reached by VALU operations
+// only: DPP quad permutes (physical xor 1, 2), DPP row rotate by 8 (xor 8)
+// and the gfx950 lane swaps v_permlane16_swap / v_permlane32_swap (xor 16,
+// xor 32).  Logical bit 5, used once (the first stage of level 6), is
+// physical xor 4: ds_swizzle.  Which element a lane holds never matters to
+// the column sort; the loads and stores around the merge use logical_lane.
 
-template <int R, int J, typename T>
-__device__ __forceinline__ void cross_half_cleaners(T (&v)[R], int lane)
+__device__ __forceinline__ int logical_lane(int p)
 {
-    if constexpr (J >= 0) {
-        const bool upper = (lane >> J) & 1;
-        if constexpr (sizeof(T) == 4) {
-            const int32_t sel = keep_selector(upper);
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                v[r] = keep_sel(v[r], xlane<(1 << J)>(v[r]), sel);
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                v[r] = keep(v[r], xlane<(1 << J)>(v[r]), upper);
-        }
-        cross_half_cleaners<R, J - 1>(v, lane);
+    return (p & 3) | (((p >> 3) & 7) << 2) | (((p >> 2) & 1) << 5);
+}
+constexpr int lane_phys_bit(int j)
+{
+    return j == 0 ? 0 : j == 1 ? 1 : j == 2 ? 3 : j == 3 ? 4 : j == 4 ? 5 : 2;
+}
+
+// In-lane compare-exchange in the direction `desc` (per lane): keys as two
+// medians with opaque selectors (the same two VALU operations as min + max),
+// pairs as one 64-bit compare and four selects.
+template <typename T> struct DirSel;
+template <> struct DirSel<int32_t> {
+    int32_t lo, hi;  // selector of the element kept at the lower / higher index
+    __device__ __forceinline__ explicit DirSel(bool desc)
+        : lo(keep_selector(desc)), hi(keep_selector(!desc)) {}
+};
+template <> struct DirSel<int64_t> {
+    bool desc;
+    __device__ __forceinline__ explicit DirSel(bool d) : desc(d) {}
+};
+
+template <typename T> __device__ __forceinline__ void cmpx_dir(T &a, T &b, const DirSel<T> &d)
+{
+    if constexpr (sizeof(T) == 4) {
+        const T lo = keep_sel(a, b, d.lo);
+        const T hi = keep_sel(a, b, d.hi);
+        a = lo;
+        b = hi;
+    } else {
+        const bool s = (b < a) != d.desc;
+        const T lo = s ? b : a;
+        const T hi = s ? a : b;
+        a = lo;
+        b = hi;
     }
 }
 
-template <int R, int D, typename T> __device__ __forceinline__ void inlane_half_cleaners(T (&v)[R])
+template <int R, int D, typename T>
+__device__ __forceinline__ void inlane_half_cleaners(T (&v)[R], const DirSel<T> &d)
 {
     if constexpr (D >= 1) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
             if (!(r & D))
-                cmpx(v[r], v[r + D]);
-        inlane_half_cleaners<R, D / 2>(v);
+                cmpx_dir(v[r], v[r + D], d);
+        inlane_half_cleaners<R, D / 2>(v, d);
     }
 }
 
-template <int R, int K, typename T>
-__device__ __forceinline__ void wave_merge_level(T (&v)[R], int lane)
+// v_permlane{16,32}_swap on (x, y): x keeps its rows (16 lanes) or halves
+// (32 lanes) with the bit clear and takes y's there; y takes x's others.  So
+// at every lane q, (x', y') is the pair {lane q, lane q ^ M} of x when q's
+// bit is clear and of y when it is set, the lower lane's element in x'.
+template <int M> __device__ __forceinline__ void lane_swap(int32_t &x, int32_t &y)
 {
-    constexpr int FLIP = (1 << K) - 1;
-    const bool upper = (lane >> (K - 1)) & 1;
-    T p[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        p[r] = xlane<FLIP>(v[R - 1 - r]);
-    if constexpr (sizeof(T) == 4) {
-        const int32_t sel = keep_selector(upper);
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            v[r] = keep_sel(v[r], p[r], sel);
+    static_assert(M == 16 || M == 32, "lane swaps exist for xor 16 and 32");
+    if constexpr (M == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+        x = (int32_t)r[0];
+        y = (int32_t)r[1];
     } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+        x = (int32_t)r[0];
+        y = (int32_t)r[1];
+    }
+}
+template <int M> __device__ __forceinline__ void lane_swap(int64_t &x, int64_t &y)
+{
+    int32_t xl = (int32_t)(uint32_t)(uint64_t)x, xh = (int32_t)((uint64_t)x >> 32);
+    int32_t yl = (int32_t)(uint32_t)(uint64_t)y, yh = (int32_t)((uint64_t)y >> 32);
+    lane_swap<M>(xl, yl);
+    lane_swap<M>(xh, yh);
+    x = (int64_t)(((uint64_t)(uint32_t)xh << 32) | (uint32_t)xl);
+    y = (int64_t)(((uint64_t)(uint32_t)yh << 32) | (uint32_t)yl);
+}
+
+// Cross-lane half-cleaner on logical bit J with direction `desc`: the lane
+// whose bit J is clear keeps the min (the max when descending).
+template <int R, int J, typename T>
+__device__ __forceinline__ void cross_half_cleaner(T (&v)[R], int lane, bool desc)
+{
+    constexpr int PB = lane_phys_bit(J);
+    constexpr int M = 1 << PB;
+    if constexpr (M == 16 || M == 32) {
+        // registers in pairs: swap so that each lane holds one lane pair of
+        // one register (lower element in the first), compare-exchange in
+        // place, swap back.  The direction is the same for both lanes of a
+        // pair (it depends on a higher bit), so each lane uses its own.
+        const DirSel<T> d(desc);
+#pragma unroll
+        for (int r = 0; r < R; r += 2) {
+            lane_swap<M>(v[r], v[r + 1]);
+            cmpx_dir(v[r], v[r + 1], d);
+            lane_swap<M>(v[r], v[r + 1]);
+        }
+    } else {
+        const bool upper = (((lane >> PB) & 1) != 0) != desc;  // keeps the max
+        if constexpr (sizeof(T) == 4) {
+            const int32_t sel = keep_selector(upper);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[r] = keep_sel(v[r], xlane<M>(v[r]), sel);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[r] = keep(v[r], xlane<M>(v[r]), upper);
+        }
+    }
+}
+
+template <int R, int J, typename T>
+__device__ __forceinline__ void cross_half_cleaners(T (&v)[R], int lane, bool desc)
+{
+    if constexpr (J >= 0) {
+        cross_half_cleaner<R, J>(v, lane, desc);
+        cross_half_cleaners<R, J - 1>(v, lane, desc);
+    }
+}
+
+// Level K of `levels`: descending output for the runs whose logical lanes
+// have bit K set, unless this is the last level.
+template <int R, int K, typename T>
+__device__ __forceinline__ void wave_merge_level(T (&v)[R], int lane, int levels)
+{
+    const bool desc = K < levels && ((lane >> lane_phys_bit(K < 6 ? K : 0)) & 1) != 0;
+    if constexpr (K == 1) {
+        // flip stage between the ascending columns of lanes l and l ^ 1
+        const bool upper = ((lane & 1) != 0) != desc;
+        T p[R];
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            v[r] = keep(v[r], p[r], upper);
+            p[r] = xlane<1>(v[R - 1 - r]);
+        if constexpr (sizeof(T) == 4) {
+            const int32_t sel = keep_selector(upper);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[r] = keep_sel(v[r], p[r], sel);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[r] = keep(v[r], p[r], upper);
+        }
+    } else {
+        cross_half_cleaners<R, K - 1>(v, lane, desc);
     }
-    cross_half_cleaners<R, K - 2>(v, lane);
-    inlane_half_cleaners<R, R / 2>(v);
+    inlane_half_cleaners<R, R / 2>(v, DirSel<T>(desc));
 }
 
 template <int R, typename T> __device__ __forceinline__ void wave_merge(T (&v)[R], int lane, int levels)
 {
-    if (levels >= 1) wave_merge_level<R, 1>(v, lane);
-    if (levels >= 2) wave_merge_level<R, 2>(v, lane);
-    if (levels >= 3) wave_merge_level<R, 3>(v, lane);
-    if (levels >= 4) wave_merge_level<R, 4>(v, lane);
-    if (levels >= 5) wave_merge_level<R, 5>(v, lane);
-    if (levels >= 6) wave_merge_level<R, 6>(v, lane);
+    if (levels >= 1) wave_merge_level<R, 1>(v, lane, levels);
+    if (levels >= 2) wave_merge_level<R, 2>(v, lane, levels);
+    if (levels >= 3) wave_merge_level<R, 3>(v, lane, levels);
+    if (levels >= 4) wave_merge_level<R, 4>(v, lane, levels);
+    if (levels >= 5) wave_merge_level<R, 5>(v, lane, levels);
+    if (levels >= 6) wave_merge_level<R, 6>(v, lane, levels);
 }
 
 // ------------------------------------------------------- merge path (a4-a6)
@@ -476,7 +572,7 @@ __device__ __forceinline__ void sort_tile_core(T *S, T (&v)[R], int t, int wave_
     column_sort<R, T, NET>(v);
     wave_merge<R>(v, lane, wave_levels);
 
-    const LdsSkew<T> W{S, wave * (64 * R) + lane * R};
+    const LdsSkew<T> W{S, wave * (64 * R) + logical_lane(lane) * R};
 #pragma unroll
     for (int r = 0; r < R; ++r)
         W[r] = v[r];

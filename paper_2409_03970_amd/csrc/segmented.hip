@@ -319,7 +319,7 @@ void seg_block_kernel(SegParams P, unsigned long long *ctrl,
         }
         __syncthreads();
         T v[R];
-        const LdsSkew<T> W{S, wave * (64 * R) + lane * R};
+        const LdsSkew<T> W{S, wave * (64 * R) + logical_lane(lane) * R};
 #pragma unroll
         for (int r = 0; r < R; ++r)
             v[r] = W[r];

@@ -56,16 +56,36 @@ def test_column_network_32_sorts_all_01_inputs():
     assert oracle.network_failures01(net, 32) == 0
 
 
-@pytest.mark.parametrize("R", [8, 16])
+@pytest.mark.parametrize("R", [4, 8, 16])
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 def test_wave_merge_levels_merge_all_sorted_halves(R, k):
-    comps = netgen.wave_merge_level(R, k)
+    # the wave merge run for k levels (the levels below k re-sort each half,
+    # the upper one descending) must merge every pair of sorted halves of
+    # R * 2^k keys: the schedule the kernels run, as a comparator network
+    comps = netgen.wave_merge(R, k)
     s = R << k
-    # the level acts on disjoint runs of s keys; check the first and the last
+    # the levels act on disjoint runs of s keys; check the first and the last
     for base in (0, R * 64 - s):
-        sub = [(a - base, b - base) for a, b in comps if base <= a < base + s]
-        assert all(0 <= b - base < s for a, b in comps if base <= a < base + s)
+        inside = [(a, b) for a, b in comps if base <= min(a, b) < base + s]
+        assert all(base <= max(a, b) < base + s for a, b in inside)
+        sub = [(a - base, b - base) for a, b in inside]
         assert oracle.merging_network_failures01(sub, s // 2, s // 2) == 0
+
+
+@pytest.mark.parametrize("R", [8, 16])
+def test_wave_merge_level_directions(R):
+    # below the last level, blocks with lane bit k set come out descending:
+    # the all-ascending merge of such a block must fail (the directions matter)
+    comps = netgen.wave_merge(R, 2)
+    flipped = [(min(a, b), max(a, b)) for a, b in comps]
+    s = R << 2
+    sub = [(a, b) for a, b in flipped if b < s]
+    assert oracle.merging_network_failures01(sub, s // 2, s // 2) > 0
+
+
+def test_lane_partners_cover_the_wave():
+    # logical lane bits map one to one onto the six physical lane bits
+    assert sorted(netgen.lane_partner(j) for j in range(6)) == [1, 2, 4, 8, 16, 32]
 
 
 def _table(text, name):
