@@ -555,6 +555,7 @@ def config5_bench():
     total, ok = 0, True
     L = hv.lib()
     for s0, s1, _ in hv.segment_groups(offs, 1 << 31):
+        log(f"  segments {s0}..{s1}")
         sz = sizes[s0:s1]
         k0, v0 = inputs.segment_pairs(sz, dists[s0:s1], s0, seed=0, device=dev)
         offs_local = inputs.offsets_from_sizes(sz)
@@ -630,27 +631,81 @@ def config5_bench():
             "learned_corank": hv.corank_stats(c)}
 
 
-def table2_bench():
-    """The paper's Table 2 on the GPU: time to leave every run of X = R * 2^k
-    keys sorted (column network, then k cross-lane merge levels), for R = 8,
-    16, 32 and, at R = 16, the three column networks of Table 1 (60 / 63 /
-    80 comparators).  2^26 uniform keys per call, one wavefront per 64 * R
-    keys; G keys/s per (R, network, X)."""
+def _graph_ms(fn, launches=20, reps=3):
+    """Time of one call of fn (which enqueues one launch) from `reps`
+    replays of a graph holding `launches` calls: no launch gaps."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()                                    # warm up outside the capture
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(launches):
+                fn()
+    torch.cuda.current_stream().wait_stream(s)
+    return _median_ms(g.replay, reps) / launches
+
+
+TABLE_N_LOG2 = 23   # 32 MiB of keys: held in the last-level cache, so the
+                    # in-register work, not HBM, sets the time
+
+
+def table2_bench(only_once=False):
+    """The paper's Table 2 on the GPU: the time to leave every run of
+    X = R * 2^k keys sorted (column network, then k cross-lane merge levels)
+    for R = 4, 8, 16, 32 and, at R = 16, the three column networks of Table 1
+    (60 / 63 / 80 comparators).  2^23 keys resident in the last-level cache,
+    256-thread workgroups, each measured as the mean of 20 launches replayed
+    from a captured graph; G keys/s per (R, network, X).  only_once: one
+    launch per variant at X = 64 R, in a fixed order (for counters)."""
     dev = torch.device("cuda", 0)
-    n = 1 << 26
+    n = 1 << TABLE_N_LOG2
     x = inputs.keys(n, "uniform", seed=0, device=dev)
     out = torch.empty_like(x)
     res = {}
-    for R, net, name in ((8, 0, "R8"), (16, 0, "R16*"), (16, 1, "R16-oddeven"),
+    for R, net, name in ((4, 0, "R4"), (8, 0, "R8"), (16, 0, "R16*"), (16, 1, "R16-oddeven"),
                          (16, 2, "R16-bitonic"), (32, 0, "R32")):
+        o = {"keys_per_lane": R, "block_threads": 256, "column_network": net}
+        if only_once:
+            hv.hvms_sort_runs_i32(x, out, int(np.log2(R * 64)), opts=o)
+            continue
         row = {}
         for k in range(0, 7):
             X = R << k
-            o = {"keys_per_lane": R, "block_threads": 256, "column_network": net}
-            ms = _median_ms(lambda: hv.hvms_sort_runs_i32(x, out, int(np.log2(X)), opts=o))
+            ms = _graph_ms(lambda: hv.hvms_sort_runs_i32(x, out, int(np.log2(X)), opts=o))
             row[f"X={X}"] = round(n / ms / 1e6, 2)
         res[name] = row
-    return res
+    torch.cuda.synchronize()
+    return {"n": n, "gkeys_per_s": res,
+            "note": "2^23 keys in the last-level cache, launches replayed from a graph"}
+
+
+def table3_bench(only_once=False):
+    """The paper's Table 3 on the GPU: the hybrid in-register merger (a run
+    per lane, cross-lane flip, then in-lane half-cleaners) against the pure
+    cross-lane one (runs across lanes, every stage a lane exchange), merging
+    pairs of sorted runs of X = 8, 16, 32 keys.  Each launch repeats the
+    merge 16 times on the registers; G merged keys/s = 16 n / time, from 20
+    launches replayed from a graph over 2^23 cache-resident keys."""
+    dev = torch.device("cuda", 0)
+    n = 1 << TABLE_N_LOG2
+    reps = 16
+    res = {}
+    for x_log2 in (3, 4, 5):
+        X = 1 << x_log2
+        x = inputs.keys(n, "uniform", seed=1, device=dev)
+        runs = hv.sort_runs(x, x_log2, opts={"keys_per_lane": 8 if X == 8 else 16,
+                                             "block_threads": 256})
+        out = torch.empty_like(runs)
+        for form, name in ((0, "hybrid"), (1, "vector")):
+            if only_once:
+                hv.hvms_merge_runs_i32(runs, out, x_log2, form, reps)
+                continue
+            ms = _graph_ms(lambda: hv.hvms_merge_runs_i32(runs, out, x_log2, form, reps))
+            res[f"2x{X}_{name}"] = {"ms": round(ms, 4),
+                                    "gkeys_per_s": round(reps * n / ms / 1e6, 1)}
+    torch.cuda.synchronize()
+    return {"n": n, "reps_per_launch": reps, "results": res}
 
 
 def measure(opts, xs, dists, out, steps, warmup):
@@ -728,6 +783,10 @@ ONLY = {
     "sort_2p28_uniform": lambda: sort_dist_bench("uniform"),
     "sort_2p28_sorted": lambda: sort_dist_bench("sorted"),
     "batched_200k_segments": lambda: batched_bench(per_array=False),
+    "table2": lambda: table2_bench(),
+    "table3": lambda: table3_bench(),
+    "table2_once": lambda: table2_bench(only_once=True),
+    "table3_once": lambda: table3_bench(only_once=True),
 }
 
 
@@ -887,7 +946,8 @@ def main():
         del xs, out, ws, M
         torch.cuda.empty_cache()
         extras = (("in_register_sort_table2", table2_bench),
-                  ("merge_table3", lambda: merge_table3_bench(n)),
+                  ("in_register_merge_table3", table3_bench),
+                  ("merge_pass_mergers", lambda: merge_table3_bench(n)),
                   ("pairs_2p28", lambda: pairs_bench(n)),
                   ("sort_by_key_p64_2p28", lambda: by_key_bench(n)),
                   ("batched_learned_pairs_50k_segments", config5_bench),

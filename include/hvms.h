@@ -55,7 +55,8 @@ enum {
  * Tuning and mode options.  A NULL pointer, or 0 in a field, selects the
  * built-in default for that field.
  *   keys_per_lane   R, keys each lane sorts in VGPRs: 8, 16 or 32 (Sec. 2.2
- *                   picks 16 registers for NEON; here R is a VGPR budget).
+ *                   picks 16 registers for NEON; here R is a VGPR budget);
+ *                   4 for key sorts (the smallest row of Table 2).
  *   block_threads   threads per block-sort workgroup: 256, 512 or 1024.  The
  *                   block tile is keys_per_lane * block_threads keys.
  *   wave_levels     cross-lane merge levels inside a wavefront, 1..6, stored
@@ -274,6 +275,22 @@ int hvms_sort_by_key_i32_p64(const int32_t *d_keys_in, const uint64_t *d_vals_in
  */
 int hvms_sort_runs_i32(const int32_t *d_in, int32_t *d_out, int64_t n, int32_t run_log2,
                        void *stream, const hvms_options *opt);
+
+/*
+ * The two in-register mergers of Table 3 (Sec. 2.4), for comparing them on
+ * the GPU: d_in holds consecutive sorted runs of X = 2^x_log2 keys (X = 8,
+ * 16 or 32); d_out receives each adjacent pair merged into one sorted run of
+ * 2X.  form 0, hybrid: one run per lane in its X VGPRs, a cross-lane flip
+ * stage, then log2(X) half-cleaners inside each lane (the serial part).
+ * form 1, vector: the runs spread across lanes (register r of lane l holds
+ * key 64r + l of its wave's 64X keys), every stage a lane exchange.  reps >= 1
+ * repeats the merge on the registers (the result is that of one merge), so
+ * a timed launch measures the merging, not the memory traffic.
+ *   n        a multiple of 256 * X (four waves of 64 X keys per workgroup).
+ *   d_in/out device int32 arrays of n keys, 16-byte aligned (may be equal).
+ */
+int hvms_merge_runs_i32(const int32_t *d_in, int32_t *d_out, int64_t n, int32_t x_log2,
+                        int32_t form, int32_t reps, void *stream);
 
 /*
  * One global merge pass: d_in holds consecutive sorted runs of run_len keys

@@ -27,7 +27,7 @@ __all__ = [
     "segment_groups", "grouped_workspace_bytes", "hvms_sort_u32", "hvms_sort_f32", "hvms_sort_pairs_u32",
     "hvms_sort_pairs_f32", "sort_keys", "sort_pairs_keys", "hvms_sort_i64", "hvms_sort_u64",
     "hvms_sort_f64", "hvms_sort_by_key_i32_p64", "sort_by_key", "hvms_segmented_status",
-    "hvms_sort_i32_noalloc", "SORT_NOALLOC_MAX_KEYS",
+    "hvms_sort_i32_noalloc", "SORT_NOALLOC_MAX_KEYS", "hvms_merge_runs_i32",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -142,6 +142,7 @@ _SIGS = {
     "hvms_cdf_train": ([_vp, _vp, _vp, _vp, _i64, _i64, _i32, _f32, _u64, _vp, _sz, _vp], _i32),
     "hvms_cdf_sample_i32": ([_vp, _i64, _i64, _u64, _vp, _vp], _i32),
     "hvms_segmented_status": ([_vp, _vp, _vp], _i32),
+    "hvms_merge_runs_i32": ([_vp, _vp, _i64, _i32, _i32, _i32, _vp], _i32),
     "hvms_sort_i32_noalloc": ([_vp, _vp, _i64, _vp, _opt], _i32),
 }
 
@@ -362,6 +363,12 @@ def hvms_sort_runs_i32(d_in, d_out, run_log2, stream=None, opts=None):
     _check("hvms_sort_runs_i32", lib().hvms_sort_runs_i32(
         _ptr(d_in, torch.int32), _ptr(d_out, torch.int32), d_in.numel(), int(run_log2),
         _stream(stream), _opts(opts)))
+
+
+def hvms_merge_runs_i32(d_in, d_out, x_log2, form, reps=1, stream=None):
+    _check("hvms_merge_runs_i32", lib().hvms_merge_runs_i32(
+        _ptr(d_in, torch.int32, "in"), _ptr(d_out, torch.int32, "out"), d_in.numel(),
+        int(x_log2), int(form), int(reps), _stream(stream)))
 
 
 def hvms_merge_pass_i32(d_in, d_out, run_len, ws=None, stream=None, opts=None):

@@ -93,7 +93,7 @@ int resolve(const hvms_options *o, bool pairs, Cfg &c)
 }
 
 struct SortWs {
-    int64_t scratch_k, scratch_v, alt_k, alt_v, coranks, records, total;
+    int64_t scratch_k, scratch_v, alt_k, alt_v, coranks, records, table, total;
 };
 
 // packed: a 64-bit key sort, whose passes ping-pong between two split
@@ -124,6 +124,10 @@ SortWs sort_ws_layout(int64_t n, bool pairs, const Cfg &c, bool packed = false)
         w.records = off;
         off += align256((ntiles + 2) * (int64_t)merge4_record_bytes());
     }
+    // the learned co-rank's model, sampled once per sort (reserved in every
+    // mode, so one workspace serves calls that switch co-rank modes)
+    w.table = off;
+    off += kCdfTableBytes;
     w.total = off;
     return w;
 }
@@ -157,6 +161,13 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
     int32_t *sk = (int32_t *)(base + w.scratch_k);
     int32_t *sv = pairs ? (int32_t *)(base + w.scratch_v) : nullptr;
     int64_t *cr = (int64_t *)(base + w.coranks);
+    CorankOpts co = c.co;
+    if (co.mode == HVMS_CORANK_LEARNED) {
+        co.table = (const float *)(base + w.table);
+        const int st0 = hip_status(launch_cdf_table(co.cdf, (float *)(base + w.table), s));
+        if (st0)
+            return st0;
+    }
     // the passes alternate between (ak, av) and (sk, sv); the last one
     // writes the caller's arrays, in packed form for a 64-bit key sort
     int32_t *ak = km.packed ? (int32_t *)(base + w.alt_k) : kout;
@@ -191,7 +202,7 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
         }
         if (p >= P2) {
             st = hip_status(launch_merge4_corank(c.TM, pairs, dk, dv, n, run, cr,
-                                                 base + w.records, c.co, s));
+                                                 base + w.records, co, s));
             if (st)
                 return st;
             trace(c, 2 + 2 * p, s);
@@ -206,7 +217,7 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
             run *= 4;
             continue;
         }
-        st = hip_status(launch_pass_corank(pairs, dk, dv, n, run, c.TM, cr, c.co, s));
+        st = hip_status(launch_pass_corank(pairs, dk, dv, n, run, c.TM, cr, co, s));
         if (st)
             return st;
         trace(c, 2 + 2 * p, s);

@@ -228,7 +228,7 @@ static hipError_t launch_bs(const int32_t *kin, const int32_t *vin, int32_t *kou
 
 bool block_sort_supported(int R, int NT, bool pairs)
 {
-    const bool r_ok = R == 8 || R == 16 || R == 32;
+    const bool r_ok = R == 8 || R == 16 || R == 32 || (R == 4 && !pairs);
     const bool nt_ok = NT == 256 || NT == 512 || NT == 1024;
     const long tile = (long)R * NT;
     const long lds = pairs ? LdsSkew<int64_t>::size(tile) * 8 : LdsSkew<int32_t>::size(tile) * 4;
@@ -271,6 +271,17 @@ hipError_t launch_block_sort(int R, int NT, bool pairs, const int32_t *kin, cons
     HVMS_BS(8, 1024)
     HVMS_BS(32, 256)
     HVMS_BS(32, 512)
+    if (R == 4 && !pairs) {  // the smallest row of Table 2 (keys only)
+        if (NT == 256)
+            return launch_bs<4, 256, int32_t>(kin, vin, kout, vout, n, wave_levels, lds_levels,
+                                              blocked, s, xin, xout);
+        if (NT == 512)
+            return launch_bs<4, 512, int32_t>(kin, vin, kout, vout, n, wave_levels, lds_levels,
+                                              blocked, s, xin, xout);
+        if (NT == 1024)
+            return launch_bs<4, 1024, int32_t>(kin, vin, kout, vout, n, wave_levels, lds_levels,
+                                               blocked, s, xin, xout);
+    }
     if (R == 32 && NT == 1024 && !pairs)
         return launch_bs<32, 1024, int32_t>(kin, vin, kout, vout, n, wave_levels, lds_levels,
                                             blocked, s, xin, xout);

@@ -36,7 +36,12 @@ struct CorankOpts {
     int radius_log2;
     const float *cdf;
     unsigned long long *stats;
+    const float *table = nullptr;  // learned mode: the model sampled (cdf_lookup)
 };
+
+// mlp.hip: the model sampled at 2^16 + 1 points (HVMS_CDF_TABLE_BYTES)
+constexpr int64_t kCdfTableBytes = ((int64_t)((1 << 16) + 1) * 4 + 255) & ~(int64_t)255;
+hipError_t launch_cdf_table(const float *params, float *table, hipStream_t s);
 
 // block_sort.hip
 bool block_sort_supported(int R, int NT, bool pairs);
@@ -78,6 +83,12 @@ hipError_t launch_corank_list(const int32_t *a, int64_t m, const int32_t *b, int
                               const int64_t *diag, int64_t count, int64_t *out,
                               const CorankOpts &o, hipStream_t s);
 
+// ablation.hip: one in-register merge level of sorted runs of 2^x_log2 keys
+hipError_t launch_merge_runs(const int32_t *in, int32_t *out, int64_t n, int x_log2, int form,
+                             int reps, hipStream_t s);
+
+constexpr int ilog2_const(int x) { return x <= 1 ? 0 : 1 + ilog2_const(x / 2); }
+
 inline int ceil_log2_host(int64_t x)
 {
     int l = 0;
@@ -88,7 +99,7 @@ inline int ceil_log2_host(int64_t x)
 
 // segmented.hip
 struct SegLayout {
-    int64_t ctrl, pieces, tiles, cr, passes, scr_k, scr_v, total, max_tiles, max_pieces;
+    int64_t ctrl, pieces, tiles, cr, passes, table, scr_k, scr_v, total, max_tiles, max_pieces;
 };
 SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool pairs);
 

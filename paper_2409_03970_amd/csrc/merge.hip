@@ -15,17 +15,18 @@
 namespace hvms {
 
 // Co-ranks of the first diagonal of every output tile of a merge pass.
-// In learned mode the 256 tiles of a block belong to at most 256 merge pairs
-// (a pair has 2*run/tm >= 1 tiles); the block first evaluates the model at
-// the four run endpoints of each of its pairs, one evaluation per thread
-// and round, so every co-rank of a pair shares them.
+// In learned mode the model comes as a table (one lookup per run endpoint),
+// or, without one, the block first evaluates the model at the four run
+// endpoints of each of its pairs (at most 64: a pair has 2*run/tm >= 1
+// tiles), one evaluation per thread and round, so every co-rank of a pair
+// shares them.
 template <typename T>
 __global__ __launch_bounds__(64) void pass_corank_kernel(PlainMap map, int64_t run, int64_t tm,
                                                           int64_t *__restrict__ cr, CorankCtl c)
 {
     __shared__ float4 F[256];
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c.mode == 1) {
+    if (c.mode == 1 && !c.table) {  // block-uniform
         const int64_t q0 = (int64_t)blockIdx.x * blockDim.x;
         const int64_t qlast = q0 + blockDim.x - 1 < map.ntiles - 1 ? q0 + blockDim.x - 1 : map.ntiles - 1;
         const int64_t p0 = q0 * tm / (2 * run), p1 = qlast * tm / (2 * run);
@@ -153,6 +154,7 @@ static CorankCtl make_ctl(const CorankOpts &o)
     c.stats = o.stats;
     c.pair_cdf = nullptr;
     c.pair_first = 0;
+    c.table = o.table;
     return c;
 }
 

@@ -24,6 +24,8 @@ struct CorankCtl {
     // and shared by the pair's co-ranks; nullptr = evaluate in place
     const float4 *pair_cdf;
     int64_t pair_first;  // pair number of pair_cdf[0]
+    // learned mode: the model sampled (cdf_lookup), or nullptr = evaluate it
+    const float *table;
 };
 
 // P(i) := A[i] <= B[d-1-i]  (A-first merge takes A[i] before B[d-1-i]).  The
@@ -63,6 +65,11 @@ __device__ int64_t predict_corank(const CorankCtl &c, FA Akey, FB Bkey, int64_t 
         fa1 = pre->y;
         fb0 = pre->z;
         fb1 = pre->w;
+    } else if (c.table) {
+        fa0 = cdf_lookup(c.table, Akey(0));
+        fa1 = cdf_lookup(c.table, Akey(m - 1));
+        fb0 = cdf_lookup(c.table, Bkey(0));
+        fb1 = cdf_lookup(c.table, Bkey(k - 1));
     } else {
         fa0 = cdf_eval(c.cdf, key_to_unit(Akey(0)));
         fa1 = cdf_eval(c.cdf, key_to_unit(Akey(m - 1)));

@@ -41,6 +41,21 @@ __global__ __launch_bounds__(256) void cdf_forward_kernel(const float *__restric
         y[i] = cdf_eval(P, x[i]);
 }
 
+// The model sampled on the unit interval: table[i] = F(i / 2^16), i <= 2^16.
+// The co-rank predictor reads it instead of evaluating the model per merge
+// pair and pass (see cdf_lookup).
+__global__ __launch_bounds__(256) void cdf_table_kernel(const float *__restrict__ p,
+                                                        float *__restrict__ table)
+{
+    __shared__ float P[NP];
+    for (int i = threadIdx.x; i < NP; i += blockDim.x)
+        P[i] = p[i];
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= kCdfTableSteps)
+        table[i] = cdf_eval(P, (float)i * (1.0f / kCdfTableSteps));
+}
+
 // Phase 1: rec[f * b + i] holds field f of sample i.
 __global__ __launch_bounds__(256) void cdf_bwd_samples_kernel(const float *__restrict__ p,
                                                               const float *__restrict__ x,
@@ -300,6 +315,13 @@ int check(void *ws, size_t bytes, int64_t need)
 }
 
 }  // namespace
+
+hipError_t launch_cdf_table(const float *params, float *table, hipStream_t s)
+{
+    hipLaunchKernelGGL(cdf_table_kernel, dim3((kCdfTableSteps + 256) / 256), dim3(256), 0, s,
+                       params, table);
+    return hipGetLastError();
+}
 
 }  // namespace hvms
 

@@ -396,6 +396,8 @@ SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool 
     o += a256((max_tiles + 1) * 8);
     L.passes = o;
     o += a256(nseg * 4);
+    L.table = o;  // the learned co-rank's model table (used in learned mode)
+    o += kCdfTableBytes;
     L.scr_k = o;
     o += a256(n_total * 4);
     L.scr_v = o;
@@ -473,7 +475,8 @@ bool segmented_supported(int R, int NT, bool pairs)
     const long tile = (long)R * NT;
     const long lds = (pairs ? LdsSkew<int64_t>::size(tile) * 8 : LdsSkew<int32_t>::size(tile) * 4) +
                      (long)NT * 16 + 8;
-    return block_sort_supported(R, NT, pairs) && lds <= 163840 && !(R == 32 && NT == 1024);
+    return block_sort_supported(R, NT, pairs) && lds <= 163840 && !(R == 32 && NT == 1024) &&
+           R != 4;
 }
 
 hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
@@ -515,6 +518,12 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
     e = launch_seg_block_any(a.R, a.NT, pairs, P, ctrl, pieces, a, sk, sv, s);
     if (e != hipSuccess)
         return e;
+    float *table = (float *)(ws + L.table);
+    if (a.co.mode == HVMS_CORANK_LEARNED && a.passes > 0) {
+        e = launch_cdf_table(a.co.cdf, table, s);
+        if (e != hipSuccess)
+            return e;
+    }
 
     for (int p = 0; p < a.passes; ++p) {
         SegMap map;
@@ -535,6 +544,7 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
         c.stats = a.co.stats;
         c.pair_cdf = nullptr;
         c.pair_first = 0;
+        c.table = a.co.mode == HVMS_CORANK_LEARNED ? table : nullptr;
         const unsigned cb = (unsigned)((L.max_tiles + 63) / 64);
         if (pairs)
             hipLaunchKernelGGL(seg_corank_kernel<int64_t>, dim3(cb), dim3(64), 0, s, map, run,

@@ -352,3 +352,29 @@ def test_inconsistent_offsets_flagged_and_nothing_written():
     out, _, st = _raw_segmented(k, offs, n, _SMALL, out=pre)
     assert st == [0, 3, 1]
     assert bool((out == -9).all())
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_learned_corank_segments_match_oracle(pairs):
+    # segments with merge passes, learned co-ranks (model table built by the
+    # call), element by element against the oracle; binary mode must agree
+    sizes = inputs.log_uniform_sizes(300, 1, 200000, seed=31)
+    offs = inputs.offsets_from_sizes(sizes)
+    n = int(offs[-1])
+    k = inputs.keys(n, "mixture", seed=31, device=DEV)
+    params = hv.fit_cdf_model(k, frac=0.02, steps=150, batch=8192, lr=3e-3, seed=31)
+    st = torch.zeros(hv.STATS_WORDS, dtype=torch.int64, device=DEV)
+    opts = {"corank_mode": hv.CORANK_LEARNED, "cdf_params": params, "radius_log2": 10,
+            "stats": st}
+    if pairs:
+        v = torch.cat([torch.arange(int(s), dtype=torch.int32) for s in sizes.tolist()]).to(DEV)
+        ko, vo = hv.segmented_sort_pairs(k, v, offs, opts=opts)
+        ek, ev = oracle.segmented_sort_pairs(k.cpu().numpy(), v.cpu().numpy(), offs.numpy())
+        assert np.array_equal(ko.cpu().numpy(), ek) and np.array_equal(vo.cpu().numpy(), ev)
+    else:
+        y = hv.segmented_sort(k, offs, opts=opts)
+        assert np.array_equal(y.cpu().numpy(),
+                              oracle.segmented_sort(k.cpu().numpy(), offs.numpy()))
+        assert torch.equal(y, hv.segmented_sort(k, offs))
+    s = hv.corank_stats(st.cpu())
+    assert s["coranks"] > 0 and s.get("predicted", 0) > 0

@@ -26,7 +26,7 @@ def _runs_from_bits(X, R):
     return bits.to(torch.int32).reshape(-1)
 
 
-@pytest.mark.parametrize("R", [8, 16])
+@pytest.mark.parametrize("R", [4, 8, 16])
 def test_column_network_all_01_inputs(R):
     # runs of R keys = the per-lane network alone; every run must come out sorted
     _say("column network 0-1, R =", R)
@@ -60,7 +60,7 @@ def _sorted_halves(X, device=DEV):
     return torch.cat([first, second], 1).reshape(-1), z1 + z2
 
 
-@pytest.mark.parametrize("R", [8, 16])
+@pytest.mark.parametrize("R", [4, 8, 16])
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 def test_wave_merge_level_all_sorted_halves(R, k):
     # runs of X = R * 2^k: the levels below k keep the sorted halves as they
@@ -458,3 +458,26 @@ def test_sort_on_side_stream_while_current_stream_allocates():
         assert np.array_equal(y.cpu().numpy(), want), rep
         assert np.array_equal(yk.cpu().numpy(), want), rep
         del junk, y, yk, yv
+
+
+# ------------------------------------------- four keys per lane (Table 2, R = 4)
+
+@pytest.mark.parametrize("NT", [256, 512, 1024])
+def test_four_keys_per_lane_sort(NT):
+    for n, dist in ((3 * 4 * NT + 77, "uniform"), (200_003, "zipf"), (4 * NT, "reverse")):
+        x = inputs.keys(n, dist, seed=NT + n, device=DEV)
+        y = hv.sort(x, opts={"keys_per_lane": 4, "block_threads": NT})
+        assert np.array_equal(y.cpu().numpy(), oracle.sort(x.cpu().numpy())), (NT, n, dist)
+    x = inputs.keys(100_000, "gaussian", seed=3, device=DEV)
+    for run_log2 in range(2, int(np.log2(4 * NT)) + 1):
+        y = hv.sort_runs(x, run_log2, opts={"keys_per_lane": 4, "block_threads": NT}).cpu().numpy()
+        xs = x.cpu().numpy()
+        X = 1 << run_log2
+        offs = np.append(np.arange(0, xs.size, X), xs.size).astype(np.int64)
+        assert np.array_equal(y, oracle.segmented_sort(xs, offs)), run_log2
+
+
+def test_four_keys_per_lane_rejected_for_pairs():
+    k = torch.zeros(100000, dtype=torch.int32, device=DEV)
+    with pytest.raises(hv.HvmsError):
+        hv.sort_pairs(k, k.clone(), opts={"keys_per_lane": 4})
