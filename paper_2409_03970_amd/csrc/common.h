@@ -479,21 +479,70 @@ __device__ __forceinline__ void serial_merge(const V &S, int alen, int boff, int
     }
 }
 
-// VT consecutive elements from position i of an LDS view.  In the skewed
-// view a run of VT <= 16 crosses at most one 16-element row, whose padding
-// shifts the elements after the crossing by one pad: each element's address
-// is one of two bases plus a constant offset.
+// VT consecutive elements from position i of an LDS view.
+//
+// int32 runs of VT <= 16 are read as the VT/4 + 1 16-byte chunks that cover
+// them, then shifted in registers by i mod 4.  Threads whose runs start
+// about VT/2 elements apart (a merge-path share per thread) would meet up to
+// 8-way bank conflicts element by element, and up to 16-way inside runs of
+// equal keys (where the tie rule makes every share one-sided); 16-byte reads
+// meet at most 2-way.  Both views keep 16-byte chunks contiguous (the skewed
+// one pads every four chunks).  Reads up to 3 elements past i + VT - 1.
+__device__ __forceinline__ const int4 *lds_chunk(const LdsPlain<int32_t> &S, int c)
+{
+    return (const int4 *)(S.S + 4 * c);
+}
+__device__ __forceinline__ const int4 *lds_chunk(const LdsSkew<int32_t> &S, int c)
+{
+    return (const int4 *)(S.S + 4 * c + LdsSkew<int32_t>::kPad * (c >> 2));
+}
+template <int VT, typename View>
+__device__ __forceinline__ void load_run_chunks(const View &S, int i, int32_t (&x)[VT])
+{
+    const int p = S.base + i;
+    const int c0 = p >> 2, sh = p & 3;
+    int32_t w[VT + 4];
+#pragma unroll
+    for (int c = 0; c < VT / 4 + 1; ++c) {
+        const int4 v = *lds_chunk(S, c0 + c);
+        w[4 * c] = v.x;
+        w[4 * c + 1] = v.y;
+        w[4 * c + 2] = v.z;
+        w[4 * c + 3] = v.w;
+    }
+    // the shift as bitwise selects on opaque masks (left as selects, the
+    // compiler turns them into an indexed array in scratch)
+    int32_t m0 = -(sh & 1), m1 = -((sh >> 1) & 1);
+    asm volatile("" : "+v"(m0), "+v"(m1));
+#pragma unroll
+    for (int k = 0; k < VT; ++k) {
+        const int32_t lo = (w[k + 1] & m0) | (w[k] & ~m0);
+        const int32_t hi = (w[k + 3] & m0) | (w[k + 2] & ~m0);
+        x[k] = (hi & m1) | (lo & ~m1);
+    }
+}
+
+// Other element types and widths: in the skewed view a run of VT <= 16
+// crosses at most one 16-element row, whose padding shifts the elements
+// after the crossing by one pad: each element's address is one of two bases
+// plus a constant offset.
 template <int VT, typename T>
 __device__ __forceinline__ void load_run(const LdsPlain<T> &S, int i, T (&x)[VT])
 {
+    if constexpr (sizeof(T) == 4 && VT <= 16) {
+        load_run_chunks<VT>(S, i, x);
+    } else {
 #pragma unroll
-    for (int k = 0; k < VT; ++k)
-        x[k] = S[i + k];
+        for (int k = 0; k < VT; ++k)
+            x[k] = S[i + k];
+    }
 }
 template <int VT, typename T>
 __device__ __forceinline__ void load_run(const LdsSkew<T> &S, int i, T (&x)[VT])
 {
-    if constexpr (VT <= 16) {
+    if constexpr (sizeof(T) == 4 && VT <= 16) {
+        load_run_chunks<VT>(S, i, x);
+    } else if constexpr (VT <= 16) {
         const int p = S.base + i;
         // bit k of cross: element k lies past the end of p's row
         uint32_t cross = 0xffffu << (16 - (p & 15));
@@ -521,8 +570,8 @@ __device__ __forceinline__ void load_run(const LdsSkew<T> &S, int i, T (&x)[VT])
 // keeps the VT smallest of the 2VT as a bitonic sequence, and log2(VT)
 // half-cleaner stages sort it.  Exact because the element order is total on
 // bit patterns (equal elements are identical, and the pad is the maximum).
-// Reads S up to VT - 1 positions past each run's end: the caller's LDS
-// array must extend that far.
+// Reads S up to VT + 2 positions past each run's end (VT - 1 for 64-bit
+// elements): the caller's LDS array must extend that far.
 // MASK = false: the caller guarantees that the VT - 1 positions after each
 // run hold the maximum of the order (sentinels), so no read needs a mask.
 template <int VT, bool MASK = true, typename V, typename T>
@@ -531,19 +580,15 @@ __device__ __forceinline__ void reg_merge(const V &S, int alen, int boff, int bl
 {
     T b[VT], xa[VT], yb[VT];
     load_run<VT>(S, i, xa);
+#pragma unroll
+    for (int k = 0; k < VT; ++k)
+        out[k] = (!MASK || i + k < alen) ? xa[k] : Traits<T>::kMax;
+    // the second run's reads after the first run's (fewer live registers)
+    asm volatile("" ::: "memory");
     load_run<VT>(S, boff + j, yb);
 #pragma unroll
-    for (int k = 0; k < VT; ++k) {
-        const T x = xa[k];
-        const T y = yb[k];
-        if constexpr (MASK) {
-            out[k] = i + k < alen ? x : Traits<T>::kMax;
-            b[k] = j + k < blen ? y : Traits<T>::kMax;
-        } else {
-            out[k] = x;
-            b[k] = y;
-        }
-    }
+    for (int k = 0; k < VT; ++k)
+        b[k] = (!MASK || j + k < blen) ? yb[k] : Traits<T>::kMax;
 #pragma unroll
     for (int k = 0; k < VT; ++k) {
         const T y = b[VT - 1 - k];
@@ -594,6 +639,85 @@ __device__ __forceinline__ void sort_tile_core(T *S, T (&v)[R], int t, int wave_
             O[k] = out[k];
         __syncthreads();
     }
+}
+
+// ------------------------------------------- presorted tiles (block stage)
+
+// Lane (lane + 1)'s value, and lane 0's for lane 63 (its caller replaces it).
+template <typename T> __device__ __forceinline__ T from_next_lane(T v, int lane)
+{
+    const int src = ((lane + 1) & 63) << 2;
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_amdgcn_ds_bpermute(src, v);
+    } else {
+        const int lo = __builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)(uint64_t)v);
+        const int hi = __builtin_amdgcn_ds_bpermute(src, (int)((uint64_t)v >> 32));
+        return (T)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    }
+}
+
+template <typename T> __device__ __forceinline__ T lane_value(T v, int src_lane)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_amdgcn_readlane(v, src_lane);
+    } else {
+        const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, src_lane);
+        const int hi = __builtin_amdgcn_readlane((int)((uint64_t)v >> 32), src_lane);
+        return (T)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    }
+}
+
+// Order of a full tile as loaded (lane l holds elements l, l + 64, ... of its
+// wave's slice): 1 nondecreasing, 2 nonincreasing (and not constant), 0
+// neither.  A cheap in-lane test (elements 64 apart) rules out most tiles;
+// waves that pass it compare lane neighbours, then the waves' boundary
+// elements are compared through S (free before the sort; one barrier, and a
+// second one when the sort follows).  Block-uniform result.
+template <int R, int NT, typename T>
+__device__ __forceinline__ int tile_order(T *S, const T (&v)[R], int lane, int wave)
+{
+    constexpr int W = NT / 64;
+    bool up = true, down = true;
+#pragma unroll
+    for (int j = 0; j + 1 < R; ++j) {
+        up = up && !(v[j + 1] < v[j]);
+        down = down && !(v[j] < v[j + 1]);
+    }
+    up = __builtin_amdgcn_ballot_w64(!up) == 0;  // wave-uniform from here
+    down = __builtin_amdgcn_ballot_w64(!down) == 0;
+    if (up || down) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            T nx = from_next_lane(v[j], lane);
+            if (j + 1 < R)
+                nx = lane == 63 ? lane_value(v[j + 1], 0) : nx;
+            const bool last = j + 1 == R && lane == 63;  // the wave's last element
+            up = up && (last || !(nx < v[j]));
+            down = down && (last || !(v[j] < nx));
+        }
+        up = __builtin_amdgcn_ballot_w64(!up) == 0;
+        down = __builtin_amdgcn_ballot_w64(!down) == 0;
+    }
+    if (lane == 0) {
+        S[4 * wave + 0] = up ? 1 : 0;
+        S[4 * wave + 1] = down ? 1 : 0;
+        S[4 * wave + 2] = v[0];
+    }
+    if (lane == 63)
+        S[4 * wave + 3] = v[R - 1];
+    __syncthreads();
+    bool bu = true, bd = true;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        bu = bu && S[4 * w] != 0;
+        bd = bd && S[4 * w + 1] != 0;
+        if (w + 1 < W) {
+            const T last = S[4 * w + 3], first = S[4 * (w + 1) + 2];
+            bu = bu && !(first < last);
+            bd = bd && !(last < first);
+        }
+    }
+    return bu ? 1 : (bd ? 2 : 0);
 }
 
 }  // namespace hvms

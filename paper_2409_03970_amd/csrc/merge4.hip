@@ -411,11 +411,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
     constexpr int TM = NT * VT;
     constexpr int CH = VT / 4 + 1;  // chunk slots per thread: TM/4 + 6 chunks at most
     // S: the four windows (TM elements, up to 24 of chunk alignment, and
-    // VT - 1 read past a window's end by reg_merge); M: the level-1 output in
-    // the skewed layout, so that rows of VT written by consecutive threads
-    // fall in distinct banks
+    // up to VT + 2 read past a window's end by reg_merge); M: the level-1
+    // output in the skewed layout, so that rows of VT written by consecutive
+    // threads fall in distinct banks (its 8 spare slots: the reads past Y's
+    // sentinels)
     __shared__ __attribute__((aligned(16))) T S[TM + 32 + VT];
-    __shared__ __attribute__((aligned(16))) T M[LdsSkew<T>::size(TM + 2 * VT)];
+    __shared__ __attribute__((aligned(16))) T M[LdsSkew<T>::size(TM + 2 * VT + 8)];
     const int t = threadIdx.x;
     const int64_t first = blockIdx.x, step = gridDim.x, last = ntiles;
     if (first >= last)
