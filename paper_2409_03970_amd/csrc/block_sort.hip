@@ -20,87 +20,6 @@
 
 namespace hvms {
 
-namespace {
-
-// Lane (lane + 1)'s value, and lane 0's for lane 63 (its caller replaces it).
-template <typename T> __device__ __forceinline__ T from_next_lane(T v, int lane)
-{
-    const int src = ((lane + 1) & 63) << 2;
-    if constexpr (sizeof(T) == 4) {
-        return __builtin_amdgcn_ds_bpermute(src, v);
-    } else {
-        const int lo = __builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)(uint64_t)v);
-        const int hi = __builtin_amdgcn_ds_bpermute(src, (int)((uint64_t)v >> 32));
-        return (T)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-    }
-}
-
-template <typename T> __device__ __forceinline__ T lane_value(T v, int src_lane)
-{
-    if constexpr (sizeof(T) == 4) {
-        return __builtin_amdgcn_readlane(v, src_lane);
-    } else {
-        const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, src_lane);
-        const int hi = __builtin_amdgcn_readlane((int)((uint64_t)v >> 32), src_lane);
-        return (T)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-    }
-}
-
-// Order of a full tile as loaded (lane l holds elements l, l + 64, ... of its
-// wave's slice): 1 nondecreasing, 2 nonincreasing (and not constant), 0
-// neither.  A cheap in-lane test (elements 64 apart) rules out most tiles;
-// waves that pass it compare lane neighbours, then the waves' boundary
-// elements are compared through S (free before the sort; one barrier, and a
-// second one when the sort follows).  Block-uniform result.
-template <int R, int NT, typename T>
-__device__ __forceinline__ int tile_order(T *S, const T (&v)[R], int lane, int wave)
-{
-    constexpr int W = NT / 64;
-    bool up = true, down = true;
-#pragma unroll
-    for (int j = 0; j + 1 < R; ++j) {
-        up = up && !(v[j + 1] < v[j]);
-        down = down && !(v[j] < v[j + 1]);
-    }
-    up = __builtin_amdgcn_ballot_w64(!up) == 0;  // wave-uniform from here
-    down = __builtin_amdgcn_ballot_w64(!down) == 0;
-    if (up || down) {
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            T nx = from_next_lane(v[j], lane);
-            if (j + 1 < R)
-                nx = lane == 63 ? lane_value(v[j + 1], 0) : nx;
-            const bool last = j + 1 == R && lane == 63;  // the wave's last element
-            up = up && (last || !(nx < v[j]));
-            down = down && (last || !(v[j] < nx));
-        }
-        up = __builtin_amdgcn_ballot_w64(!up) == 0;
-        down = __builtin_amdgcn_ballot_w64(!down) == 0;
-    }
-    if (lane == 0) {
-        S[4 * wave + 0] = up ? 1 : 0;
-        S[4 * wave + 1] = down ? 1 : 0;
-        S[4 * wave + 2] = v[0];
-    }
-    if (lane == 63)
-        S[4 * wave + 3] = v[R - 1];
-    __syncthreads();
-    bool bu = true, bd = true;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        bu = bu && S[4 * w] != 0;
-        bd = bd && S[4 * w + 1] != 0;
-        if (w + 1 < W) {
-            const T last = S[4 * w + 3], first = S[4 * (w + 1) + 2];
-            bu = bu && !(first < last);
-            bd = bd && !(last < first);
-        }
-    }
-    return bu ? 1 : (bd ? 2 : 0);
-}
-
-}  // namespace
-
 template <int R, int NT, typename T, int NET = 0, int PKM = 0>
 __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restrict__ kin,
                                                         const int32_t *__restrict__ vin,

@@ -99,7 +99,8 @@ inline int ceil_log2_host(int64_t x)
 
 // segmented.hip
 struct SegLayout {
-    int64_t ctrl, pieces, tiles, cr, passes, table, scr_k, scr_v, total, max_tiles, max_pieces;
+    int64_t ctrl, pieces, fulls, tiles, cr, passes, table, scr_k, scr_v, total, max_tiles,
+        max_pieces, max_full;
 };
 SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool pairs);
 

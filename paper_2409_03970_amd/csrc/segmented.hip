@@ -47,6 +47,8 @@ enum : int {
     C_OVER,                         // segments with P_s above the enqueued passes
     C_SKIP,                         // segments skipped: offsets outside [0, n_total] or decreasing
     C_BAD,                          // 1: offsets inconsistent with n_total, nothing sorted
+    C_FULL,                         // full pieces (TILE keys of a longer segment)
+    C_FCUR,                         // scatter cursor of the full-piece list
     C_LCNT = 80,                    // large segments with P_s == P
     C_TCNT = C_LCNT + kMaxP,        // merge tiles of those segments
     C_TCUR = C_TCNT + kMaxP,        // tile-list cursors per P
@@ -72,7 +74,7 @@ __device__ __forceinline__ int ceil_log2(int64_t x)
 struct SegParams {
     const int64_t *off;
     int64_t nseg, n_total;
-    int64_t max_pieces, max_tiles;  // list capacities in the workspace
+    int64_t max_pieces, max_tiles, max_full;  // list capacities in the workspace
     int tile_log2, r_log2, nb;  // nb = buckets = tile_log2 - r_log2 + 1
     int passes;                 // merge passes enqueued by the host
     int64_t tm;
@@ -92,7 +94,7 @@ __global__ void seg_init_kernel(unsigned long long *ctrl)
 
 __global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned long long *ctrl)
 {
-    __shared__ unsigned long long cnt[kMaxBuckets], lcnt[kMaxP], tcnt[kMaxP], over, skip;
+    __shared__ unsigned long long cnt[kMaxBuckets], lcnt[kMaxP], tcnt[kMaxP], over, skip, full;
     for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
         lcnt[i] = 0;
         tcnt[i] = 0;
@@ -102,6 +104,7 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned lo
     if (threadIdx.x == 0) {
         over = 0;
         skip = 0;
+        full = 0;
     }
     __syncthreads();
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,9 +121,14 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned lo
             if (size <= tile) {
                 atomicAdd(&cnt[bucket_of(P, size)], 1ull);
             } else {
+                // full pieces go to the full-piece list, a ragged rest to the
+                // bucket of its own size
                 const int64_t np = (size + tile - 1) / tile;
                 const int ps = ceil_log2(np);
-                atomicAdd(&cnt[P.nb - 1], (unsigned long long)np);
+                const int64_t nfull = size / tile, rest = size - nfull * tile;
+                atomicAdd(&full, (unsigned long long)nfull);
+                if (rest)
+                    atomicAdd(&cnt[bucket_of(P, rest)], 1ull);
                 atomicAdd(&lcnt[ps], 1ull);
                 atomicAdd(&tcnt[ps], (unsigned long long)((size + P.tm - 1) / P.tm));
                 if (ps > P.passes)
@@ -134,6 +142,8 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned lo
             atomicAdd(&ctrl[C_OVER], over);
         if (skip)
             atomicAdd(&ctrl[C_SKIP], skip);
+        if (full)
+            atomicAdd(&ctrl[C_FULL], full);
     }
     for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
         if (lcnt[i])
@@ -154,7 +164,8 @@ __global__ void seg_plan_kernel(SegParams P, unsigned long long *ctrl)
         pieces += ctrl[C_CNT + b];
     for (int p = 0; p < kMaxP; ++p)
         tiles_total += ctrl[C_TCNT + p];
-    if (pieces > (unsigned long long)P.max_pieces || tiles_total > (unsigned long long)P.max_tiles) {
+    if (pieces > (unsigned long long)P.max_pieces || tiles_total > (unsigned long long)P.max_tiles ||
+        ctrl[C_FULL] > (unsigned long long)P.max_full) {
         // inconsistent offsets / n_total: leave every task and pass empty,
         // keep the counts of the status words and raise the flag
         const unsigned long long over = ctrl[C_OVER], skip = ctrl[C_SKIP];
@@ -189,21 +200,24 @@ __global__ void seg_plan_kernel(SegParams P, unsigned long long *ctrl)
 }
 
 __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned long long *ctrl,
-                                                          Piece *pieces, int2 *tiles,
-                                                          int32_t *passes)
+                                                          Piece *pieces, Piece *fulls,
+                                                          int2 *tiles, int32_t *passes)
 {
     __shared__ unsigned long long cnt[kMaxBuckets], bbase[kMaxBuckets], tcnt[kMaxP], tbase[kMaxP];
+    __shared__ unsigned long long fcnt, fbase;
     for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
         tcnt[i] = 0;
         if (i < kMaxBuckets)
             cnt[i] = 0;
     }
+    if (threadIdx.x == 0)
+        fcnt = 0;
     __syncthreads();
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tile = (int64_t)1 << P.tile_log2;
-    int64_t size = 0, np = 0, nt = 0, o = 0;
+    int64_t size = 0, nfull = 0, nt = 0, o = 0;
     int b = -1, ps = 0;
-    unsigned long long mine = 0, tmine = 0;
+    unsigned long long mine = 0, tmine = 0, fmine = 0;
     if (s < P.nseg) {
         o = P.off[s];
         const int64_t e = P.off[s + 1];
@@ -211,15 +225,17 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
         if (size > 0) {
             if (size <= tile) {
                 b = bucket_of(P, size);
-                np = 1;
             } else {
-                b = P.nb - 1;
-                np = (size + tile - 1) / tile;
-                ps = ceil_log2(np);
+                nfull = size / tile;
+                const int64_t rest = size - nfull * tile;
+                b = rest ? bucket_of(P, rest) : -1;
+                ps = ceil_log2((size + tile - 1) / tile);
                 nt = (size + P.tm - 1) / P.tm;
                 tmine = atomicAdd(&tcnt[ps], (unsigned long long)nt);
+                fmine = atomicAdd(&fcnt, (unsigned long long)nfull);
             }
-            mine = atomicAdd(&cnt[b], (unsigned long long)np);
+            if (b >= 0)
+                mine = atomicAdd(&cnt[b], 1ull);
         }
         // a segment needing more passes than are enqueued runs the enqueued
         // ones (and is counted in C_OVER): its pieces start where that pass
@@ -233,22 +249,86 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
         if (i < kMaxBuckets && cnt[i])
             bbase[i] = ctrl[C_BASE + i] + atomicAdd(&ctrl[C_CUR + i], cnt[i]);
     }
+    if (threadIdx.x == 0 && fcnt)
+        fbase = atomicAdd(&ctrl[C_FCUR], fcnt);
     __syncthreads();
-    if (b >= 0) {
-        const int64_t first = bbase[b] + mine;
-        const int dst = ((ps < P.passes ? ps : P.passes) & 1) ? 1 : 0;
-        for (int64_t i = 0; i < np && first + i < P.max_pieces; ++i) {
-            Piece pc;
-            pc.off = o + i * tile;
-            const int64_t rem = size - i * tile;
-            pc.len = (int32_t)(rem < tile ? rem : tile);
-            pc.dst = dst;
-            pieces[first + i] = pc;
-        }
-        if (nt) {
-            const int64_t tf = tbase[ps] + tmine;
-            for (int64_t j = 0; j < nt && tf + j < P.max_tiles; ++j)
-                tiles[tf + j] = make_int2((int)s, (int)j);
+    const int dst = ((ps < P.passes ? ps : P.passes) & 1) ? 1 : 0;
+    if (b >= 0 && bbase[b] + mine < (unsigned long long)P.max_pieces) {
+        // the segment itself, or the ragged rest after its full pieces
+        Piece pc;
+        pc.off = o + nfull * tile;
+        pc.len = (int32_t)(size - nfull * tile);
+        pc.dst = dst;
+        pieces[bbase[b] + mine] = pc;
+    }
+    for (int64_t i = 0; i < nfull && fbase + fmine + i < (unsigned long long)P.max_full; ++i) {
+        Piece pc;
+        pc.off = o + i * tile;
+        pc.len = (int32_t)tile;
+        pc.dst = dst;
+        fulls[fbase + fmine + i] = pc;
+    }
+    if (nt) {
+        const int64_t tf = tbase[ps] + tmine;
+        for (int64_t j = 0; j < nt && tf + j < P.max_tiles; ++j)
+            tiles[tf + j] = make_int2((int)s, (int)j);
+    }
+}
+
+// The full pieces of long segments: a tile of exactly R * NT keys each, sorted
+// like a tile of the plain block stage (strided register loads, the
+// presorted-tile test, column sort, in-register merge levels, LDS merge
+// levels), one workgroup per entry of the full-piece list.  R and NT are
+// chosen for the tile size (R = 32 where it fits), independent of the packed
+// kernel's, which must also serve tiny segments.
+template <int R, int NT, typename T>
+__global__ __launch_bounds__(NT) void seg_full_kernel(int wave_levels, int lds_levels,
+                                                      const unsigned long long *ctrl,
+                                                      const Piece *__restrict__ fulls,
+                                                      const int32_t *__restrict__ ik,
+                                                      const int32_t *__restrict__ iv,
+                                                      int32_t *__restrict__ ok,
+                                                      int32_t *__restrict__ ov,
+                                                      int32_t *__restrict__ sk,
+                                                      int32_t *__restrict__ sv)
+{
+    constexpr int TILE = R * NT;
+    __shared__ __attribute__((aligned(16))) T S[LdsSkew<T>::size(TILE)];
+    const LdsSkew<T> Z{S, 0};
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int64_t nfull = (int64_t)ctrl[C_FULL];
+    {
+        const int64_t q = blockIdx.x;  // one piece per workgroup
+        if (q >= nfull)
+            return;
+        const Piece pc = fulls[q];
+        // the piece's arrays from its first key on: 32-bit indices below
+        const int32_t *pk = ik + pc.off;
+        const int32_t *pv = sizeof(T) == 8 ? iv + pc.off : nullptr;
+        int32_t *dk = (pc.dst ? sk : ok) + pc.off;
+        int32_t *dv = sizeof(T) == 8 ? (pc.dst ? sv : ov) + pc.off : nullptr;
+        T v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            v[j] = load_elem<T>(pk, pv, wave * (64 * R) + 64 * j + lane);
+        const int ord = tile_order<R, NT, T>(S, v, lane, wave);
+        if (ord != 0) {  // block-uniform: stored as loaded, or reversed
+            const int rel = wave * (64 * R) + lane;
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int p = rel + 64 * j;
+                store_elem<T>(dk, dv, ord == 1 ? p : TILE - 1 - p, v[j]);
+            }
+        } else {
+            __syncthreads();  // S is the sort's from here
+            // level counts as arguments (not constants), as in the plain
+            // block stage: unrolled LDS levels cost registers
+            sort_tile_core<R, NT>(S, v, t, wave_levels, lds_levels);
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                store_elem<T>(dk, dv, t + NT * j, Z[t + NT * j]);
         }
     }
 }
@@ -384,12 +464,15 @@ SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool 
     SegLayout L{};
     const int64_t tile = (int64_t)R * NT;
     const int64_t max_pieces = nseg + 2 * (n_total / tile) + 2;
+    const int64_t max_full = n_total / tile + 1;
     const int64_t max_tiles = n_total / TM + n_total / tile + 2;
     int64_t o = 0;
     L.ctrl = o;
     o += a256(C_WORDS * 8);
     L.pieces = o;
     o += a256(max_pieces * (int64_t)sizeof(Piece));
+    L.fulls = o;
+    o += a256(max_full * (int64_t)sizeof(Piece));
     L.tiles = o;
     o += a256(max_tiles * 8);
     L.cr = o;
@@ -406,6 +489,7 @@ SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool 
     L.total = o;
     L.max_tiles = max_tiles;
     L.max_pieces = max_pieces;
+    L.max_full = max_full;
     return L;
 }
 
@@ -444,6 +528,43 @@ static hipError_t launch_seg_merge(const SegMap &map, int64_t run, const int64_t
     hipLaunchKernelGGL((seg_merge_kernel<NT, VT, T>), dim3((unsigned)grid), dim3(NT), 0, s, map,
                        run, cr, n_abs, xcd ? 1 : 0);
     return hipGetLastError();
+}
+
+template <int R, int NT, typename T>
+static hipError_t launch_seg_full(const unsigned long long *ctrl, const Piece *fulls,
+                                  int64_t max_full, const SegArgs &a, int32_t *sk, int32_t *sv,
+                                  hipStream_t s)
+{
+    // one workgroup per possible full piece; those past the count exit
+    const int64_t grid = max_full;
+    const int lanes_log2 = NT == 256 ? 8 : NT == 512 ? 9 : 10;
+    hipLaunchKernelGGL((seg_full_kernel<R, NT, T>), dim3((unsigned)grid), dim3(NT), 0, s, 6,
+                       lanes_log2 - 6, ctrl, fulls, a.kin, a.vin, a.kout, a.vout, sk, sv);
+    return hipGetLastError();
+}
+
+// The full-piece kernel's shape for a tile of `tile` keys: 32 keys per lane
+// where the tile has at least 256 lanes of them, else fewer.
+static hipError_t launch_seg_full_any(int64_t tile, bool pairs, const unsigned long long *ctrl,
+                                      const Piece *fulls, int64_t max_full, const SegArgs &a,
+                                      int32_t *sk, int32_t *sv, hipStream_t s)
+{
+    if (pairs) {
+        switch (tile) {
+        case 2048: return launch_seg_full<8, 256, int64_t>(ctrl, fulls, max_full, a, sk, sv, s);
+        case 4096: return launch_seg_full<16, 256, int64_t>(ctrl, fulls, max_full, a, sk, sv, s);
+        case 8192: return launch_seg_full<16, 512, int64_t>(ctrl, fulls, max_full, a, sk, sv, s);
+        case 16384: return launch_seg_full<16, 1024, int64_t>(ctrl, fulls, max_full, a, sk, sv, s);
+        }
+    } else {
+        switch (tile) {
+        case 2048: return launch_seg_full<8, 256, int32_t>(ctrl, fulls, max_full, a, sk, sv, s);
+        case 4096: return launch_seg_full<16, 256, int32_t>(ctrl, fulls, max_full, a, sk, sv, s);
+        case 8192: return launch_seg_full<32, 256, int32_t>(ctrl, fulls, max_full, a, sk, sv, s);
+        case 16384: return launch_seg_full<32, 512, int32_t>(ctrl, fulls, max_full, a, sk, sv, s);
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 static hipError_t launch_seg_block_any(int R, int NT, bool pairs, const SegParams &P,
@@ -491,6 +612,7 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
     P.n_total = a.n_total;
     P.max_pieces = L.max_pieces;
     P.max_tiles = L.max_tiles;
+    P.max_full = L.max_full;
     P.tile_log2 = tile_log2;
     P.r_log2 = r_log2;
     P.nb = tile_log2 - r_log2 + 1;
@@ -499,6 +621,7 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
     char *ws = (char *)a.ws;
     unsigned long long *ctrl = (unsigned long long *)(ws + L.ctrl);
     Piece *pieces = (Piece *)(ws + L.pieces);
+    Piece *fulls = (Piece *)(ws + L.fulls);
     int2 *tiles = (int2 *)(ws + L.tiles);
     int64_t *cr = (int64_t *)(ws + L.cr);
     int32_t *passes = (int32_t *)(ws + L.passes);
@@ -509,12 +632,15 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
     const unsigned sb = (unsigned)((a.nseg + 255) / 256);
     hipLaunchKernelGGL(seg_count_kernel, dim3(sb), dim3(256), 0, s, P, ctrl);
     hipLaunchKernelGGL(seg_plan_kernel, dim3(1), dim3(64), 0, s, P, ctrl);
-    hipLaunchKernelGGL(seg_scatter_kernel, dim3(sb), dim3(256), 0, s, P, ctrl, pieces, tiles,
-                       passes);
+    hipLaunchKernelGGL(seg_scatter_kernel, dim3(sb), dim3(256), 0, s, P, ctrl, pieces, fulls,
+                       tiles, passes);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
 
+    e = launch_seg_full_any(tile, pairs, ctrl, fulls, L.max_full, a, sk, sv, s);
+    if (e != hipSuccess)
+        return e;
     e = launch_seg_block_any(a.R, a.NT, pairs, P, ctrl, pieces, a, sk, sv, s);
     if (e != hipSuccess)
         return e;
