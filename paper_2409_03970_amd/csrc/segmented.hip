@@ -155,47 +155,65 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned lo
     }
 }
 
-__global__ void seg_plan_kernel(SegParams P, unsigned long long *ctrl)
+__global__ __launch_bounds__(64) void seg_plan_kernel(SegParams P, unsigned long long *ctrl)
 {
-    if (threadIdx.x != 0)
-        return;
-    unsigned long long pieces = 0, tiles_total = 0;
-    for (int b = 0; b < P.nb; ++b)
-        pieces += ctrl[C_CNT + b];
-    for (int p = 0; p < kMaxP; ++p)
-        tiles_total += ctrl[C_TCNT + p];
-    if (pieces > (unsigned long long)P.max_pieces || tiles_total > (unsigned long long)P.max_tiles ||
-        ctrl[C_FULL] > (unsigned long long)P.max_full) {
+    // one wave: the counts are read once into LDS, the prefix sums over the
+    // (at most 48) pass counts are taken by one thread each
+    __shared__ unsigned long long cnt[kMaxBuckets], tcnt[kMaxP];
+    __shared__ int bad;
+    const int t = threadIdx.x;
+    if (t < kMaxBuckets)
+        cnt[t] = t < P.nb ? ctrl[C_CNT + t] : 0;
+    if (t < kMaxP)
+        tcnt[t] = ctrl[C_TCNT + t];
+    __syncthreads();
+    if (t == 0) {
+        unsigned long long pieces = 0, tiles_total = 0;
+        for (int b = 0; b < P.nb; ++b)
+            pieces += cnt[b];
+        for (int p = 0; p < kMaxP; ++p)
+            tiles_total += tcnt[p];
+        bad = pieces > (unsigned long long)P.max_pieces ||
+              tiles_total > (unsigned long long)P.max_tiles ||
+              ctrl[C_FULL] > (unsigned long long)P.max_full;
+    }
+    __syncthreads();
+    if (bad) {
         // inconsistent offsets / n_total: leave every task and pass empty,
         // keep the counts of the status words and raise the flag
         const unsigned long long over = ctrl[C_OVER], skip = ctrl[C_SKIP];
-        for (int i = 0; i < C_WORDS; ++i)
+        __syncthreads();
+        for (int i = t; i < C_WORDS; i += blockDim.x)
             ctrl[i] = 0;
-        ctrl[C_OVER] = over;
-        ctrl[C_SKIP] = skip;
-        ctrl[C_BAD] = 1;
+        __syncthreads();
+        if (t == 0) {
+            ctrl[C_OVER] = over;
+            ctrl[C_SKIP] = skip;
+            ctrl[C_BAD] = 1;
+        }
         return;
     }
-    unsigned long long base = 0, task = 0;
-    for (int b = P.nb - 1; b >= 0; --b) {  // largest bucket first
-        const unsigned long long slots = (unsigned long long)1 << (P.tile_log2 - (P.r_log2 + b));
-        ctrl[C_BASE + b] = base;
-        ctrl[C_TASK + b] = task;
-        base += ctrl[C_CNT + b];
-        task += (ctrl[C_CNT + b] + slots - 1) / slots;
+    if (t == 0) {
+        unsigned long long base = 0, task = 0;
+        for (int b = P.nb - 1; b >= 0; --b) {  // largest bucket first
+            const unsigned long long slots = (unsigned long long)1
+                                             << (P.tile_log2 - (P.r_log2 + b));
+            ctrl[C_BASE + b] = base;
+            ctrl[C_TASK + b] = task;
+            base += cnt[b];
+            task += (cnt[b] + slots - 1) / slots;
+        }
+        ctrl[C_NTASK] = task;
     }
-    ctrl[C_NTASK] = task;
-    unsigned long long tb = 0;
-    for (int p = kMaxP - 1; p >= 1; --p) {  // tile list ordered by P descending
-        ctrl[C_TBASE + p] = tb;
-        tb += ctrl[C_TCNT + p];
-    }
-    // pass p covers the segments with P_s > p: a prefix of the tile list
-    for (int p = 0; p < kMaxP; ++p) {
-        unsigned long long t = 0;
-        for (int q = p + 1; q < kMaxP; ++q)
-            t += ctrl[C_TCNT + q];
-        ctrl[C_PASS + p] = t;
+    if (t < kMaxP) {
+        // tile list ordered by P descending: base of P = t; pass t covers
+        // the segments with P_s > t, a prefix of the list
+        unsigned long long above = 0;
+        for (int q = t + 1; q < kMaxP; ++q)
+            above += tcnt[q];
+        if (t >= 1)
+            ctrl[C_TBASE + t] = above;
+        ctrl[C_PASS + t] = above;
     }
 }
 
