@@ -348,8 +348,11 @@ def _mode_stats(x, out, ws, opts, params, mode, radius=12):
     return r
 
 
-def corank_modes(xs, dists, out, ws, opts):
-    """Binary vs learned vs linear co-rank on the same 2^28 inputs."""
+def corank_modes(xs, dists, out, ws, opts, opts4=None, ws4=None):
+    """Binary vs learned vs linear co-rank on the same 2^28 inputs: in the
+    best two-way shape (the two-way co-rank is the one the model predicts)
+    and, with opts4, in the tuned four-way shape (where the prediction picks
+    the grid interval of each tile's splitter)."""
     res = {}
     for x, d in zip(xs, dists):
         t0 = torch.cuda.Event(enable_timing=True)
@@ -362,6 +365,11 @@ def corank_modes(xs, dists, out, ws, opts):
         for name, mode in (("binary", hv.CORANK_BINARY), ("learned", hv.CORANK_LEARNED),
                            ("linear", hv.CORANK_LINEAR)):
             r[name] = _mode_stats(x, out, ws, opts, params, mode)
+        if opts4 is not None:
+            r["four_way"] = {name: _mode_stats(x, out, ws4, opts4, params, mode)
+                             for name, mode in (("binary", hv.CORANK_BINARY),
+                                                ("learned", hv.CORANK_LEARNED),
+                                                ("linear", hv.CORANK_LINEAR))}
         res[d] = r
     return res
 
@@ -538,7 +546,7 @@ def small_bench():
             "graph_gkeys_per_s": round(n / gms / 1e6, 2), "options": opts}
 
 
-def config5_bench():
+def config5_bench(max_groups=None, per_segment=True):
     """50,000 segments, sizes log-uniform in [256, 4194304] (about 2.2e10
     (key, index) pairs, each segment one of the six distributions), generated
     super-group by super-group (about 2^31 pairs each, bounded scratch).
@@ -554,7 +562,9 @@ def config5_bench():
     stats = torch.zeros(hv.STATS_WORDS, dtype=torch.int64, device=dev)
     total, ok = 0, True
     L = hv.lib()
-    for s0, s1, _ in hv.segment_groups(offs, 1 << 31):
+    for gi, (s0, s1, _) in enumerate(hv.segment_groups(offs, 1 << 31)):
+        if max_groups is not None and gi >= max_groups:
+            break
         log(f"  segments {s0}..{s1}")
         sz = sizes[s0:s1]
         k0, v0 = inputs.segment_pairs(sz, dists[s0:s1], s0, seed=0, device=dev)
@@ -597,6 +607,11 @@ def config5_bench():
         ok &= bool(torch.equal(res["learned"][0], res["binary"][0]))
         ok &= bool(torch.equal(res["learned"][1], res["binary"][1]))
         del res, gws
+        if not per_segment:
+            total += k0.numel()
+            del k0, v0
+            torch.cuda.empty_cache()
+            continue
         # one plain pair sort per segment, same inputs
         k, v = k0.clone(), v0.clone()
         maxs = int(sz.max())
@@ -626,7 +641,8 @@ def config5_bench():
             "batched_binary_ms": round(t["binary"], 1),
             "batched_binary_gpairs_per_s": round(total / t["binary"] / 1e6, 2),
             "per_segment_plain_ms": round(t["per_segment"], 1),
-            "per_segment_gpairs_per_s": round(total / t["per_segment"] / 1e6, 2),
+            "per_segment_gpairs_per_s": (round(total / t["per_segment"] / 1e6, 2)
+                                         if t["per_segment"] else None),
             "training_ms_all_groups": round(t["train"], 1),
             "learned_corank": hv.corank_stats(c)}
 
@@ -783,6 +799,7 @@ ONLY = {
     "sort_2p28_uniform": lambda: sort_dist_bench("uniform"),
     "sort_2p28_sorted": lambda: sort_dist_bench("sorted"),
     "batched_200k_segments": lambda: batched_bench(per_array=False),
+    "batched_learned_pairs_first_group": lambda: config5_bench(max_groups=1, per_segment=False),
     "table2": lambda: table2_bench(),
     "table3": lambda: table3_bench(),
     "table2_once": lambda: table2_bench(only_once=True),
@@ -905,7 +922,9 @@ def main():
                 oc = {k: int(v) for k, v in oc.items()}
             wsc = torch.empty(max(hv.lib().hvms_sort_workspace_bytes(n, 0, hv._opts(oc)), 1),
                               dtype=torch.uint8, device=dev)
-            rec["corank_modes_2p28"] = dict(corank_modes(xs, dists, out, wsc, oc), options=oc)
+            rec["corank_modes_2p28"] = dict(
+                corank_modes(xs, dists, out, wsc, oc, opts if ways == 4 else None, ws),
+                options=oc, options_four_way=opts if ways == 4 else None)
             del wsc
         except Exception as e:  # an extra must never cost the headline line
             rec["corank_modes_2p28"] = {"error": repr(e)}

@@ -372,6 +372,9 @@ int hvms_segmented_status(const void *d_ws, int64_t *d_status, void *stream);
  * W1[32] b1[32] W2[32][32] (row = output unit) b2[32] W3[32] b3[1]. */
 #define HVMS_CDF_PARAMS 1153
 
+/* HVMS_CDF_PARAMS as a call, for bindings that do not read the header. */
+int64_t hvms_cdf_param_count(void);
+
 /* y[i] = F(x[i]) for i < b.  Device arrays. */
 int hvms_cdf_forward(const float *d_params, const float *d_x, float *d_y, int64_t b,
                      void *stream);

@@ -28,6 +28,7 @@ __all__ = [
     "hvms_sort_pairs_f32", "sort_keys", "sort_pairs_keys", "hvms_sort_i64", "hvms_sort_u64",
     "hvms_sort_f64", "hvms_sort_by_key_i32_p64", "sort_by_key", "hvms_segmented_status",
     "hvms_sort_i32_noalloc", "SORT_NOALLOC_MAX_KEYS", "hvms_merge_runs_i32",
+    "hvms_cdf_param_count",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -143,6 +144,7 @@ _SIGS = {
     "hvms_cdf_sample_i32": ([_vp, _i64, _i64, _u64, _vp, _vp], _i32),
     "hvms_segmented_status": ([_vp, _vp, _vp], _i32),
     "hvms_merge_runs_i32": ([_vp, _vp, _i64, _i32, _i32, _i32, _vp], _i32),
+    "hvms_cdf_param_count": ([], _i64),
     "hvms_sort_i32_noalloc": ([_vp, _vp, _i64, _vp, _opt], _i32),
 }
 
@@ -409,6 +411,10 @@ def hvms_segmented_status(ws, status, stream=None):
         raise ValueError("status needs 3 int64 entries")
     _check("hvms_segmented_status", lib().hvms_segmented_status(
         _ptr(ws, None, "ws"), _ptr(status, torch.int64, "status"), _stream(stream)))
+
+
+def hvms_cdf_param_count():
+    return int(lib().hvms_cdf_param_count())
 
 
 def hvms_cdf_forward(params, x, y, stream=None):

@@ -157,6 +157,10 @@ __device__ __forceinline__ void rank2(const VRun<T> &X, int64_t kx, int64_t lx, 
 
 // Co-ranks (x, a, c) of diagonal d (a multiple of tm) of X (+) Y.
 //
+// With a prediction (learned or linear mode), stage 1 first tests the two
+// grid points around the predicted splitter together and only bisects the
+// side that remains when they do not bracket it.
+//
 // x is the first m in [lo0, hi0) with Y[d-1-m] < X[m] (hi0 if none).
 // Stage 1 searches the sample grid: the two-way co-ranks a(k*tm) of X and
 // c(k*tm) of Y, which the two-way co-rank kernel computes for every tile of
@@ -171,9 +175,46 @@ __device__ __forceinline__ void rank2(const VRun<T> &X, int64_t kx, int64_t lx, 
 // (A cooperative variant with 16 lanes per tile and 16-way splits cuts the
 // dependent depth about threefold but issues several times the scattered
 // loads, and measured slower.)
+// The key of element 0 and of the last element of a virtual run (min of the
+// first keys, max of the last keys of its two runs).
+template <typename T>
+__device__ __forceinline__ void vrun_ends(const VRun<T> &V, int32_t &first, int32_t &last)
+{
+    const int32_t *pk = V.pk, *qk = V.qk;
+    if (V.np == 0) {
+        first = qk[0];
+        last = qk[V.nq - 1];
+    } else if (V.nq == 0) {
+        first = pk[0];
+        last = pk[V.np - 1];
+    } else {
+        first = min(pk[0], qk[0]);
+        last = max(pk[V.np - 1], qk[V.nq - 1]);
+    }
+}
+
+// Predicted split of diagonal d between X and Y (c.mode != 0): the
+// learned or proportional co-rank prediction of the two-way pass, applied
+// to the virtual runs X and Y through their end keys (for the model: where
+// its CDF puts them), i.e. the splitter of the four runs at rank d.
+template <typename T>
+__device__ int64_t predict_split(const Group<T> &G, int64_t d, const CorankCtl &c)
+{
+    const int64_t nx = G.X.len(), ny = G.Y.len();
+    if (nx == 0 || ny == 0)
+        return d < nx ? d : nx;
+    int32_t x0, x1, y0, y1;
+    vrun_ends<T>(G.X, x0, x1);
+    vrun_ends<T>(G.Y, y0, y1);
+    auto XK = [=](int64_t i) { return i == 0 ? x0 : x1; };
+    auto YK = [=](int64_t i) { return i == 0 ? y0 : y1; };
+    return predict_corank(c, XK, YK, nx, ny, d, nullptr);
+}
+
 template <typename T>
 __device__ Quad quad_corank(const Group<T> &G, int64_t d, int64_t tm, const int64_t *grid,
-                            int64_t gx, int64_t gy, unsigned &probes)
+                            int64_t gx, int64_t gy, unsigned &probes,
+                            const CorankCtl *pred = nullptr)
 {
     const VRun<T> &X = G.X, &Y = G.Y;
     const int64_t nx = X.len(), ny = Y.len();
@@ -190,14 +231,32 @@ __device__ Quad quad_corank(const Group<T> &G, int64_t d, int64_t tm, const int6
 
     // stage 1: first grid point k*tm in [lo0, hi0) whose test holds
     int64_t klo = (lo0 + mask) / tm, khi = (hi0 + mask) / tm;
-    while (klo < khi) {
-        const int64_t k = (klo + khi) >> 1, m = k * tm;
+    auto test = [&](int64_t k) {  // Y[d-1-m] < X[m] at m = k*tm, k in [klo, khi)
+        const int64_t m = k * tm;
         const int64_t am = grid[gx + k];  // m < hi0 <= nx
         const int64_t ym = d - m;         // in [1, ny], a multiple of tm
         const int64_t cm = ym == ny ? Y.np : grid[gy + ym / tm];
         bool f;
         ++probes;
-        if (Y.last(ym, cm) < X.at(m, am, f))
+        return Y.last(ym, cm) < X.at(m, am, f);
+    };
+    if (pred && khi - klo > 2) {
+        // predicted splitter: test the grid points around it together; the
+        // answer is exact when they bracket it, else the bisection goes on
+        // in the remaining side
+        int64_t k = predict_split<T>(G, d, *pred) / tm;
+        k = k < klo ? klo : (k > khi - 2 ? khi - 2 : k);
+        const bool t0 = test(k), t1 = test(k + 1);
+        if (t0)
+            khi = k;
+        else if (t1)
+            klo = khi = k + 1;
+        else
+            klo = k + 2;
+    }
+    while (klo < khi) {
+        const int64_t k = (klo + khi) >> 1;
+        if (test(k))
             khi = k;
         else
             klo = k + 1;
@@ -340,7 +399,8 @@ __global__ __launch_bounds__(64) void quad_corank_kernel(const int32_t *__restri
                                                           int64_t ntiles, int lg4run,
                                                           const int64_t *__restrict__ grid,
                                                           TileRec *__restrict__ out,
-                                                          unsigned long long *stats)
+                                                          unsigned long long *stats,
+                                                          CorankCtl pc)
 {
     const int l = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 63 + l;
@@ -350,7 +410,8 @@ __global__ __launch_bounds__(64) void quad_corank_kernel(const int32_t *__restri
         const int64_t o0 = g * tm;
         G = group_of<T>(kin, vin, n, run, o0 >> lg4run);
         unsigned probes = 0;
-        q = quad_corank<T>(G, o0 - G.gb, tm, grid, G.gb / tm, (G.gb + 2 * run) / tm, probes);
+        q = quad_corank<T>(G, o0 - G.gb, tm, grid, G.gb / tm, (G.gb + 2 * run) / tm, probes,
+                           pc.mode != 0 ? &pc : nullptr);
         if (stats && l < 63) {
             atomicAdd(stats + 0, 1ull);
             atomicAdd(stats + 1, (unsigned long long)probes);
@@ -653,10 +714,22 @@ static hipError_t launch_quad_corank(const int32_t *kin, const int32_t *vin, int
     const int64_t ntiles = (n + tm - 1) / tm;
     // one thread per tile, one wave per workgroup: the chains of dependent
     // probes spread over all CUs (256-thread workgroups left half of them
-    // idle at 2^28 keys and measured 3 % slower per sort)
+    // idle at 2^28 keys and measured 3 % slower per sort).  In the learned
+    // and linear modes each tile first tests the grid interval its predicted
+    // splitter falls in (the kernel counts the stats itself).
+    CorankCtl pc;
+    pc.mode = o.mode;
+    pc.radius_log2 = o.radius_log2;
+    pc.cdf = o.cdf;
+    pc.stats = nullptr;
+    pc.pair_cdf = nullptr;
+    pc.pair_first = 0;
+    pc.table = o.table;
+    if (pc.mode == 1 && !pc.table)  // no table: proportional split
+        pc.mode = 2;
     hipLaunchKernelGGL(quad_corank_kernel<T>, dim3((unsigned)((ntiles + 62) / 63)), dim3(64), 0,
                        s, kin, vin, n, run, tm, ntiles, ilog2_pow2(4 * run), grid, (TileRec *)rec,
-                       o.stats);
+                       o.stats, pc);
     return hipGetLastError();
 }
 

@@ -329,6 +329,8 @@ using namespace hvms;
 
 extern "C" {
 
+int64_t hvms_cdf_param_count(void) { return HVMS_CDF_PARAMS; }
+
 int hvms_cdf_forward(const float *d_params, const float *d_x, float *d_y, int64_t b, void *stream)
 {
     if (b < 0 || (b > 0 && (!d_params || !d_x || !d_y)))

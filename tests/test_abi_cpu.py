@@ -190,6 +190,11 @@ def test_sort_noalloc_argument_errors():
     assert "#define HVMS_SORT_NOALLOC_MAX_KEYS (1 << 22)" in text
 
 
+def test_cdf_param_count_matches_header_and_oracle():
+    from oracle import mlp
+    assert hv.hvms_cdf_param_count() == hv.CDF_PARAMS == mlp.N_PARAMS == 1153
+
+
 def test_cdf_argument_errors():
     L = hv.lib()
     assert L.hvms_cdf_forward(FAKE, FAKE, FAKE, 0, None) == 0
