@@ -56,9 +56,18 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
             v[r] = W[r];
         __syncthreads();
     } else if (tile0 + TILE <= n) {
+        if constexpr (!PI && !IO) {
+            // buffer loads: a lane offset plus a wave-uniform one per element
+            const TileIO<T> io(kin + tile0, vin ? vin + tile0 : nullptr, TILE);
+            const int wb = __builtin_amdgcn_readfirstlane(wave) * (64 * R);
 #pragma unroll
-        for (int j = 0; j < R; ++j)
-            v[j] = load_elem<T, PI, IO>(kin, vin, wave0 + 64 * j + lane);
+            for (int j = 0; j < R; ++j)
+                v[j] = io.load(lane, wb + 64 * j);
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                v[j] = load_elem<T, PI, IO>(kin, vin, wave0 + 64 * j + lane);
+        }
         if (key_map_on(xin)) {  // wave-uniform
 #pragma unroll
             for (int j = 0; j < R; ++j)
@@ -88,7 +97,22 @@ __global__ __launch_bounds__(NT) void block_sort_kernel(const int32_t *__restric
 
     sort_tile_core<R, NT, T, NET>(S, v, t, wave_levels, lds_levels);
 
-    if (tile0 + TILE <= n && !key_map_on(xout)) {
+    if (tile0 + TILE <= n && !PO) {
+        // element t + NT*j of the tile sits at a constant distance from
+        // element t in the skewed layout (NT is a multiple of 16)
+        const TileIO<T> io(kout + tile0, vout ? vout + tile0 : nullptr, TILE);
+        const T *zt = S + LdsSkew<T>::pos(t);
+        constexpr int ZS = LdsSkew<T>::size(NT);
+        if (!key_map_on(xout)) {
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                io.store(t, NT * j, zt[ZS * j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                io.store(t, NT * j, map_elem(zt[ZS * j], xout));
+        }
+    } else if (tile0 + TILE <= n && !key_map_on(xout)) {
 #pragma unroll
         for (int j = 0; j < R; ++j)
             store_elem<T, PO>(kout, vout, tile0 + t + NT * j, Z[t + NT * j]);

@@ -64,6 +64,46 @@ __device__ __forceinline__ void store_elem(int32_t *__restrict__ k, int32_t *__r
     }
 }
 
+// Buffer resource over `bytes` bytes from p: raw layout (stride 0, no
+// format conversion; the gfx9 descriptor's third word).  An access through
+// it adds a 32-bit VGPR byte offset, a wave-uniform SGPR offset and an
+// immediate to the base, so the unrolled loads and stores of a tile need no
+// 64-bit address arithmetic per element.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+// One tile's elements through buffer resources: int32 keys, or key/value
+// pairs in two int32 arrays (packed 64-bit arrays and index values keep
+// load_elem / store_elem).  Offsets are in elements: vo per lane, so
+// wave-uniform.
+template <typename T> struct TileIO {
+    __amdgpu_buffer_rsrc_t k, v;
+    __device__ __forceinline__ TileIO(const int32_t *kb, const int32_t *vb, int n)
+        : k(raw_rsrc(kb, 4u * (uint32_t)n)), v(raw_rsrc(sizeof(T) == 8 ? vb : kb, 4u * (uint32_t)n))
+    {
+    }
+    __device__ __forceinline__ T load(int vo, int so) const
+    {
+        const int32_t x = __builtin_amdgcn_raw_buffer_load_b32(k, 4 * vo, 4 * so, 0);
+        if constexpr (sizeof(T) == 4)
+            return x;
+        else
+            return pack_pair(x, __builtin_amdgcn_raw_buffer_load_b32(v, 4 * vo, 4 * so, 0));
+    }
+    __device__ __forceinline__ void store(int vo, int so, T x) const
+    {
+        if constexpr (sizeof(T) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(x, k, 4 * vo, 4 * so, 0);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b32(pair_key(x), k, 4 * vo, 4 * so, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(pair_val(x), v, 4 * vo, 4 * so, 0);
+        }
+    }
+};
+
 // Key maps (see KeyMap): the element with its key mapped; pads are never
 // mapped, so the callers apply these to real elements only.
 __device__ __forceinline__ bool key_map_on(KeyMap m) { return (m.um | m.fm | m.fl) != 0; }
@@ -479,6 +519,36 @@ __device__ __forceinline__ void serial_merge(const V &S, int alen, int boff, int
     }
 }
 
+// The serial merge of the block stage's LDS levels: runs A = [base, base +
+// run) and B = [base + run, base + 2 run) of a skewed tile of TILE elements,
+// R outputs from co-ranks (i, j).  Branch-free: a run counts as exhausted
+// once its next position reaches its end (the value read there is never
+// used); the next position read is clamped to the tile's last element, the
+// only read that could leave the array (A's end is B's start).
+template <int R, int TILE, typename T>
+__device__ __forceinline__ void merge_pair_rows(const T *S, int base, int run, int i, int j,
+                                                T (&out)[R])
+{
+    int pa = base + i, pb = base + run + j;
+    const int aend = base + run, bend = base + 2 * run;
+    T a = S[LdsSkew<T>::pos(pa)];
+    T b = S[LdsSkew<T>::pos(pb < TILE - 1 ? pb : TILE - 1)];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const bool takeB = (pb < bend) & ((pa >= aend) | (b < a));
+        out[k] = takeB ? b : a;
+        if (k + 1 < R) {
+            pa += takeB ? 0 : 1;
+            pb += takeB ? 1 : 0;
+            int r = takeB ? pb : pa;
+            r = r < TILE - 1 ? r : TILE - 1;
+            const T nx = S[LdsSkew<T>::pos(r)];
+            a = takeB ? a : nx;
+            b = takeB ? nx : b;
+        }
+    }
+}
+
 // VT consecutive elements from position i of an LDS view.
 //
 // int32 runs of VT <= 16 are read as the VT/4 + 1 16-byte chunks that cover
@@ -631,7 +701,7 @@ __device__ __forceinline__ void sort_tile_core(T *S, T (&v)[R], int t, int wave_
         const LdsSkew<T> P{S, base};
         const int i = lds_corank(P, run, run, run, d);
         T out[R];
-        serial_merge<R>(P, run, run, run, i, d - i, out);
+        merge_pair_rows<R, R * NT>(S, base, run, i, d - i, out);
         __syncthreads();
         const LdsSkew<T> O{S, o0};
 #pragma unroll

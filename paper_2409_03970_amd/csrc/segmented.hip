@@ -312,7 +312,6 @@ __global__ __launch_bounds__(NT) void seg_full_kernel(int wave_levels, int lds_l
 {
     constexpr int TILE = R * NT;
     __shared__ __attribute__((aligned(16))) T S[LdsSkew<T>::size(TILE)];
-    const LdsSkew<T> Z{S, 0};
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
@@ -327,10 +326,13 @@ __global__ __launch_bounds__(NT) void seg_full_kernel(int wave_levels, int lds_l
         const int32_t *pv = sizeof(T) == 8 ? iv + pc.off : nullptr;
         int32_t *dk = (pc.dst ? sk : ok) + pc.off;
         int32_t *dv = sizeof(T) == 8 ? (pc.dst ? sv : ov) + pc.off : nullptr;
+        // buffer loads and stores: a lane offset plus a wave-uniform one
+        const TileIO<T> in(pk, pv, TILE), out(dk, dv, TILE);
+        const int wb = __builtin_amdgcn_readfirstlane(wave) * (64 * R);
         T v[R];
 #pragma unroll
         for (int j = 0; j < R; ++j)
-            v[j] = load_elem<T>(pk, pv, wave * (64 * R) + 64 * j + lane);
+            v[j] = in.load(lane, wb + 64 * j);
         const int ord = tile_order<R, NT, T>(S, v, lane, wave);
         if (ord != 0) {  // block-uniform: stored as loaded, or reversed
             const int rel = wave * (64 * R) + lane;
@@ -344,9 +346,12 @@ __global__ __launch_bounds__(NT) void seg_full_kernel(int wave_levels, int lds_l
             // level counts as arguments (not constants), as in the plain
             // block stage: unrolled LDS levels cost registers
             sort_tile_core<R, NT>(S, v, t, wave_levels, lds_levels);
+            // element t + NT*j sits at a constant distance from element t
+            const T *zt = S + LdsSkew<T>::pos(t);
+            constexpr int ZS = LdsSkew<T>::size(NT);
 #pragma unroll
             for (int j = 0; j < R; ++j)
-                store_elem<T>(dk, dv, t + NT * j, Z[t + NT * j]);
+                out.store(t, NT * j, zt[ZS * j]);
         }
     }
 }
