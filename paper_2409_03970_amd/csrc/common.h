@@ -549,6 +549,31 @@ __device__ __forceinline__ void merge_pair_rows(const T *S, int base, int run, i
     }
 }
 
+// serial_merge without index clamps, for callers whose LDS array extends at
+// least one element past the end of either run: a run counts as exhausted
+// once its next position reaches its end (the value read there is never
+// used), so the loop is branch-free.
+template <int VT, typename V, typename T>
+__device__ __forceinline__ void serial_merge_open(const V &S, int alen, int boff, int blen, int i,
+                                                  int j, T (&out)[VT])
+{
+    int pa = i, pb = boff + j;
+    const int bend = boff + blen;
+    T a = S[pa], b = S[pb];
+#pragma unroll
+    for (int k = 0; k < VT; ++k) {
+        const bool takeB = (pb < bend) & ((pa >= alen) | (b < a));
+        out[k] = takeB ? b : a;
+        if (k + 1 < VT) {
+            pa += takeB ? 0 : 1;
+            pb += takeB ? 1 : 0;
+            const T nx = S[takeB ? pb : pa];
+            a = takeB ? a : nx;
+            b = takeB ? nx : b;
+        }
+    }
+}
+
 // VT consecutive elements from position i of an LDS view.
 //
 // int32 runs of VT <= 16 are read as the VT/4 + 1 16-byte chunks that cover

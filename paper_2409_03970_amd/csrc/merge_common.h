@@ -598,8 +598,8 @@ __device__ __forceinline__ void merge_pipe_body(const Map &map, int64_t run,
         T out[VT];
         if constexpr (BIT)
             reg_merge<VT>(A, cur.acnt, boff, cur.bcnt, i, diag - i, out);
-        else
-            serial_merge<VT>(A, cur.acnt, boff, cur.bcnt, i, diag - i, out);
+        else  // windows are followed by chunk padding: reads one past stay in S
+            serial_merge_open<VT>(A, cur.acnt, boff, cur.bcnt, i, diag - i, out);
         // the last pass of a uint32 / float32 sort maps the keys back: keys in
         // registers here, pairs where the packed pairs are split for the
         // store (each keeps the 16-byte stores and the register budget)
