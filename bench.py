@@ -521,6 +521,23 @@ def learned_bench():
     res["sorted_ok"] = bool(res["binary"]["output_certified"] and
                             res["learned"]["output_equals_binary"] and
                             res["linear"]["output_equals_binary"])
+    res["options"] = opts
+    # the same modes in the best two-way shape, where every co-rank of a
+    # pass is a predicted two-way co-rank (in the four-way shape the model
+    # also picks each tile's grid interval)
+    o2 = tune.tuned_options("sort", n, two_way=True)
+    if o2 and o2.get("merge_ways", 2) == 2 and o2 != opts:
+        ws2 = hv._workspace(hv.lib().hvms_sort_workspace_bytes(n, 0, hv._opts(o2)), dev)
+        tw = {"options": o2}
+        for name, mode in (("binary", hv.CORANK_BINARY), ("learned", hv.CORANK_LEARNED),
+                           ("linear", hv.CORANK_LINEAR)):
+            r = _mode_stats(x, out, ws2, o2, params, mode, radius=13)
+            r["output_equals_binary"] = bool(torch.equal(out, ref))
+            tw[name] = r
+        res["two_way"] = tw
+        res["sorted_ok"] = bool(res["sorted_ok"] and all(tw[m]["output_equals_binary"]
+                                                         for m in ("binary", "learned", "linear")))
+        del ws2
     return res
 
 

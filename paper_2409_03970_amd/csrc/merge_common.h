@@ -238,6 +238,22 @@ __device__ __forceinline__ PairGeo pair_geo(const TileRef &r, int64_t tm, int64_
     return P;
 }
 
+// A (key, value) element of two int32 arrays, compared without forming it:
+// keys first, values only where the keys tie (the order of pack_pair: both
+// words signed), so a co-rank probe on key-value runs reads 8 bytes, not 16,
+// unless the keys are equal.
+struct LazyPair {
+    const int32_t *k, *v;
+    int64_t i;
+};
+__device__ __forceinline__ bool operator<(const LazyPair &x, const LazyPair &y)
+{
+    const int32_t a = x.k[x.i], b = y.k[y.i];
+    if (a != b)
+        return a < b;
+    return x.v[x.i] < y.v[y.i];
+}
+
 // Co-rank of a tile's first diagonal (one thread per tile).
 template <typename T, typename Map>
 __device__ __forceinline__ void tile_corank(const Map &map, int64_t q, int64_t run, int64_t tm,
@@ -252,13 +268,19 @@ __device__ __forceinline__ void tile_corank(const Map &map, int64_t q, int64_t r
     const int32_t *ak = r.ik + r.base + P.pb, *bk = ak + run;
     const int32_t *av = r.iv ? r.iv + r.base + P.pb : nullptr;
     const int32_t *bv = av ? av + run : nullptr;
-    auto A = [=](int64_t i) { return load_elem<T>(ak, av, i); };
-    auto B = [=](int64_t i) { return load_elem<T>(bk, bv, i); };
     auto Ak = [=](int64_t i) { return ak[i]; };
     auto Bk = [=](int64_t i) { return bk[i]; };
     // pairs start at multiples of 2 * run from the sequence start
     const float4 *pre = c.pair_cdf ? c.pair_cdf + (P.pb / (2 * run) - c.pair_first) : nullptr;
-    cr[q] = find_corank<T>(c, A, B, Ak, Bk, P.alen, P.blen, P.d0, pre);
+    if constexpr (sizeof(T) == 8) {
+        auto A = [=](int64_t i) { return LazyPair{ak, av, i}; };
+        auto B = [=](int64_t i) { return LazyPair{bk, bv, i}; };
+        cr[q] = find_corank<T>(c, A, B, Ak, Bk, P.alen, P.blen, P.d0, pre);
+    } else {
+        auto A = [=](int64_t i) { return ak[i]; };
+        auto B = [=](int64_t i) { return bk[i]; };
+        cr[q] = find_corank<T>(c, A, B, Ak, Bk, P.alen, P.blen, P.d0, pre);
+    }
 }
 
 // ------------------------------------------- persistent, pipelined merge pass
