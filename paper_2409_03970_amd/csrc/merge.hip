@@ -15,18 +15,17 @@
 namespace hvms {
 
 // Co-ranks of the first diagonal of every output tile of a merge pass.
-// In learned mode the model comes as a table (one lookup per run endpoint),
-// or, without one, the block first evaluates the model at the four run
-// endpoints of each of its pairs (at most 64: a pair has 2*run/tm >= 1
-// tiles), one evaluation per thread and round, so every co-rank of a pair
-// shares them.
+// In learned mode the block first takes the model's CDF (table lookup, or
+// the network without a table) at the four run endpoints of each of its
+// pairs (at most 64: a pair has 2*run/tm >= 1 tiles), one per thread and
+// round, so every co-rank of a pair shares them.
 template <typename T>
 __global__ __launch_bounds__(64) void pass_corank_kernel(PlainMap map, int64_t run, int64_t tm,
                                                           int64_t *__restrict__ cr, CorankCtl c)
 {
     __shared__ float4 F[256];
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c.mode == 1 && !c.table) {  // block-uniform
+    if (c.mode == 1) {  // block-uniform
         const int64_t q0 = (int64_t)blockIdx.x * blockDim.x;
         const int64_t qlast = q0 + blockDim.x - 1 < map.ntiles - 1 ? q0 + blockDim.x - 1 : map.ntiles - 1;
         const int64_t p0 = q0 * tm / (2 * run), p1 = qlast * tm / (2 * run);
@@ -40,7 +39,9 @@ __global__ __launch_bounds__(64) void pass_corank_kernel(PlainMap map, int64_t r
             int64_t idx = w == 0 ? pb : w == 1 ? pb + alen - 1 : w == 2 ? pb + run : pb + run + blen - 1;
             if (w >= 2 && blen == 0)
                 idx = pb + alen - 1;
-            ((float *)&F[e / 4])[w] = cdf_eval(c.cdf, key_to_unit(map.ik[idx]));
+            const int32_t key = map.ik[idx];
+            ((float *)&F[e / 4])[w] =
+                c.table ? cdf_lookup(c.table, key) : cdf_eval(c.cdf, key_to_unit(key));
         }
         __syncthreads();
         c.pair_cdf = F;

@@ -121,7 +121,10 @@ __device__ int64_t find_corank(const CorankCtl &c, FA A, FB B, KA Akey, KB Bkey,
     const int64_t hi = d < m ? d : m;
     unsigned probes = 0, fallback = 0;
     int64_t res, pred = 0;
-    const bool predicted = c.mode != 0 && hi - lo > 2;
+    // predict only where the bracket is a small part of the feasible range:
+    // the prediction's reads and the two bracket tests cost about as much as
+    // the three bisection steps they can save against a range of 8 brackets
+    const bool predicted = c.mode != 0 && hi - lo > ((int64_t)8 << c.radius_log2);
     if (!predicted) {
         res = binary_corank<T>(A, B, d, lo, hi, probes);
     } else {
@@ -254,10 +257,25 @@ __device__ __forceinline__ bool operator<(const LazyPair &x, const LazyPair &y)
     return x.v[x.i] < y.v[y.i];
 }
 
-// Co-rank of a tile's first diagonal (one thread per tile).
+// The model's CDF at the first and last keys of a pair's runs A and B (the
+// learned prediction's inputs, shared by every tile of the pair).
+__device__ __forceinline__ float4 pair_cdf_of(const CorankCtl &c, const int32_t *ak, int64_t alen,
+                                              const int32_t *bk, int64_t blen)
+{
+    auto f = [&](int32_t k) {
+        return c.table ? cdf_lookup(c.table, k) : cdf_eval(c.cdf, key_to_unit(k));
+    };
+    const int32_t a0 = ak[0], a1 = ak[alen - 1];
+    const int32_t b0 = blen ? bk[0] : a1, b1 = blen ? bk[blen - 1] : a1;
+    return make_float4(f(a0), f(a1), f(b0), f(b1));
+}
+
+// Co-rank of a tile's first diagonal (one thread per tile).  pre: the pair's
+// CDF values (pair_cdf_of), or nullptr.
 template <typename T, typename Map>
 __device__ __forceinline__ void tile_corank(const Map &map, int64_t q, int64_t run, int64_t tm,
-                                            int64_t *__restrict__ cr, const CorankCtl &c)
+                                            int64_t *__restrict__ cr, const CorankCtl &c,
+                                            const float4 *pair_pre = nullptr)
 {
     const TileRef r = map.at(q);
     const PairGeo P = pair_geo(r, tm, run);
@@ -271,7 +289,8 @@ __device__ __forceinline__ void tile_corank(const Map &map, int64_t q, int64_t r
     auto Ak = [=](int64_t i) { return ak[i]; };
     auto Bk = [=](int64_t i) { return bk[i]; };
     // pairs start at multiples of 2 * run from the sequence start
-    const float4 *pre = c.pair_cdf ? c.pair_cdf + (P.pb / (2 * run) - c.pair_first) : nullptr;
+    const float4 *pre = pair_pre ? pair_pre
+                        : c.pair_cdf ? c.pair_cdf + (P.pb / (2 * run) - c.pair_first) : nullptr;
     if constexpr (sizeof(T) == 8) {
         auto A = [=](int64_t i) { return LazyPair{ak, av, i}; };
         auto B = [=](int64_t i) { return LazyPair{bk, bv, i}; };

@@ -444,13 +444,54 @@ void seg_block_kernel(SegParams P, unsigned long long *ctrl,
     }
 }
 
+// One wave per workgroup, one tile per lane.  In learned mode the model's
+// CDF at a pair's four run endpoints is taken once per pair and wave, by the
+// pair's first lane, and handed to the pair's other lanes.
 template <typename T>
 __global__ __launch_bounds__(64) void seg_corank_kernel(SegMap map, int64_t run, int64_t tm,
                                                          int64_t *__restrict__ cr, CorankCtl c)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < map.count())
-        tile_corank<T>(map, q, run, tm, cr, c);
+    const int lane = threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + lane;
+    const bool valid = q < map.count();
+    if (c.mode != 1) {
+        if (valid)
+            tile_corank<T>(map, q, run, tm, cr, c);
+        return;
+    }
+    // the pair of this tile: segment and pair base (the run pair index)
+    int seg = -1;
+    int64_t pb = -1;
+    TileRef r{};
+    PairGeo P{};
+    if (valid) {
+        r = map.at(q);
+        P = pair_geo(r, tm, run);
+        seg = map.tiles[q].x;
+        pb = P.pb;
+    }
+    const int prev = (lane + 63) & 63;
+    const int pseg = __builtin_amdgcn_ds_bpermute(prev << 2, seg);
+    const int pl = __builtin_amdgcn_ds_bpermute(prev << 2, (int)(uint32_t)pb);
+    const int ph = __builtin_amdgcn_ds_bpermute(prev << 2, (int)(pb >> 32));
+    const int64_t ppb = (int64_t)(uint32_t)pl | ((int64_t)ph << 32);
+    const bool leader = valid && (lane == 0 || pseg != seg || ppb != pb);
+    float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (leader && P.alen > 0) {
+        const int32_t *ak = r.ik + r.base + P.pb;
+        f = pair_cdf_of(c, ak, P.alen, ak + run, P.blen);
+    }
+    // each lane's leader: the highest leader lane at or below it
+    const uint64_t lm = __builtin_amdgcn_ballot_w64(leader);
+    const uint64_t below = lm & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+    const int src = below ? 63 - __builtin_clzll(below) : lane;
+    float4 g;
+    g.x = __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(f.x)));
+    g.y = __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(f.y)));
+    g.z = __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(f.z)));
+    g.w = __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(f.w)));
+    if (valid)
+        tile_corank<T>(map, q, run, tm, cr, c, &g);
 }
 
 template <int NT, int VT, typename T>
