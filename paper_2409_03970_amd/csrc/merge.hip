@@ -25,7 +25,8 @@ __global__ __launch_bounds__(64) void pass_corank_kernel(PlainMap map, int64_t r
 {
     __shared__ float4 F[256];
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c.mode == 1) {  // block-uniform
+    // (only where the runs are long enough for a prediction: see find_corank)
+    if (c.mode == 1 && run > ((int64_t)8 << c.radius_log2)) {  // block-uniform
         const int64_t q0 = (int64_t)blockIdx.x * blockDim.x;
         const int64_t qlast = q0 + blockDim.x - 1 < map.ntiles - 1 ? q0 + blockDim.x - 1 : map.ntiles - 1;
         const int64_t p0 = q0 * tm / (2 * run), p1 = qlast * tm / (2 * run);

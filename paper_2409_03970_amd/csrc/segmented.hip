@@ -454,7 +454,7 @@ __global__ __launch_bounds__(64) void seg_corank_kernel(SegMap map, int64_t run,
     const int lane = threadIdx.x;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + lane;
     const bool valid = q < map.count();
-    if (c.mode != 1) {
+    if (c.mode != 1 || run <= ((int64_t)8 << c.radius_log2)) {  // no prediction (find_corank)
         if (valid)
             tile_corank<T>(map, q, run, tm, cr, c);
         return;
