@@ -439,6 +439,31 @@ def test_presorted_pairs_and_other_key_types(descending):
 
 # ----------------------------------------------- conveniences on a side stream
 
+@pytest.mark.parametrize("shape", [(32, 512), (16, 512), (32, 256), (16, 1024)])
+@pytest.mark.parametrize("order", ["descending_blocks", "ascending_blocks", "one_sided_ties"])
+def test_lds_levels_exhausted_runs(shape, order):
+    # tiles whose wave runs have disjoint key ranges (each run random inside,
+    # so the tile is not presorted): at every LDS merge level one run of a
+    # pair is exhausted part way, including at the tile's last element, the
+    # read the branch-free serial merge clamps; ties between runs where the
+    # A-first rule makes every share one-sided
+    R, NT = shape
+    tile, wave = R * NT, 64 * R
+    n = 3 * tile + 4 * wave + 77
+    rng = np.random.default_rng(R + NT)
+    blk = np.arange(n) // wave
+    if order == "descending_blocks":
+        x = (1000 - blk) * 100000 + rng.integers(0, 100000, n)
+    elif order == "ascending_blocks":
+        x = blk * 100000 + rng.integers(0, 100000, n)
+    else:
+        x = np.where(blk % 2 == 0, 7, rng.integers(-5, 7, n))
+    x = x.astype(np.int32)
+    _say("exhausted runs", shape, order)
+    y = hv.sort(torch.from_numpy(x).to(DEV), opts={"keys_per_lane": R, "block_threads": NT})
+    assert np.array_equal(y.cpu().numpy(), oracle.sort(x))
+
+
 def test_sort_on_side_stream_while_current_stream_allocates():
     # the convenience wrappers allocate their workspace for the stream the
     # kernels run on: memory freed when the call returns must not be handed
