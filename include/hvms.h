@@ -68,6 +68,9 @@ enum {
  *   radius_log2     learned/linear mode: the bounded search first brackets
  *                   the prediction with +-2^radius_log2 and falls back to
  *                   binary search when the co-rank lies outside (default 12).
+ *                   A co-rank whose feasible range is at most 8 brackets
+ *                   (8 * 2^radius_log2 positions) takes plain binary search:
+ *                   there the prediction would save no probes.
  *   stats           optional device array of HVMS_STATS_WORDS uint64 counters
  *                   the co-rank kernels add to (see HVMS_STAT_*), or NULL.
  *   merge_variant   global merge kernel: 0 default, 1 one tile per workgroup,
