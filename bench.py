@@ -563,7 +563,7 @@ def small_bench():
             "graph_gkeys_per_s": round(n / gms / 1e6, 2), "options": opts}
 
 
-def config5_bench(max_groups=None, per_segment=True):
+def config5_bench(max_groups=None, per_segment=True, base_opts=None):
     """50,000 segments, sizes log-uniform in [256, 4194304] (about 2.2e10
     (key, index) pairs, each segment one of the six distributions), generated
     super-group by super-group (about 2^31 pairs each, bounded scratch).
@@ -576,6 +576,10 @@ def config5_bench(max_groups=None, per_segment=True):
     dists = inputs.segment_distributions(nseg, seed=0)
     offs = inputs.offsets_from_sizes(sizes).tolist()
     t = {"learned": 0.0, "binary": 0.0, "per_segment": 0.0, "train": 0.0}
+    from paper_2409_03970_amd import tune
+    # the tuned shape for batched key-value segments (else the defaults)
+    base = dict(base_opts if base_opts is not None
+                else (tune.tuned_options("segmented_pairs", 1 << 31) or {}))
     stats = torch.zeros(hv.STATS_WORDS, dtype=torch.int64, device=dev)
     total, ok = 0, True
     L = hv.lib()
@@ -597,11 +601,11 @@ def config5_bench(max_groups=None, per_segment=True):
             torch.cuda.synchronize()
             t["train"] += a.elapsed_time(b)
             params[gi] = p
-            return {"corank_mode": hv.CORANK_LEARNED, "cdf_params": p, "stats": stats}
+            return dict(base, corank_mode=hv.CORANK_LEARNED, cdf_params=p, stats=stats)
 
         res = {}
         # the group workspace is allocated before the timed calls
-        gws = hv._workspace(hv.grouped_workspace_bytes(offs_local, 1 << 30), dev)
+        gws = hv._workspace(hv.grouped_workspace_bytes(offs_local, 1 << 30, base or None), dev)
         for mode in ("learned", "binary"):
             k, v = k0.clone(), v0.clone()
             torch.cuda.synchronize()
@@ -609,9 +613,10 @@ def config5_bench(max_groups=None, per_segment=True):
                 hv.segmented_sort_pairs_grouped(k, v, offs_local, 1 << 30, opts_for_group=learned,
                                                 ws=gws)
                 k, v = k0.clone(), v0.clone()      # first run trained the models
-                fn = (lambda kg, gi: {"corank_mode": hv.CORANK_LEARNED, "cdf_params": params[gi]})
+                fn = (lambda kg, gi: dict(base, corank_mode=hv.CORANK_LEARNED,
+                                          cdf_params=params[gi]))
             else:
-                fn = None
+                fn = (lambda kg, gi: dict(base)) if base else None
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
@@ -652,7 +657,7 @@ def config5_bench(max_groups=None, per_segment=True):
         del k, v, k0, v0, ws
         torch.cuda.empty_cache()
     c = stats.cpu().tolist()
-    return {"pairs": total, "segments": nseg, "learned_equals_binary": ok,
+    return {"pairs": total, "segments": nseg, "options": base, "learned_equals_binary": ok,
             "batched_learned_ms": round(t["learned"], 1),
             "batched_learned_gpairs_per_s": round(total / t["learned"] / 1e6, 2),
             "batched_binary_ms": round(t["binary"], 1),

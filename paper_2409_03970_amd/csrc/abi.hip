@@ -641,7 +641,7 @@ int64_t hvms_segmented_workspace_bytes(int64_t n_total, int64_t nseg, int64_t ma
         return st;
     if (nseg == 0)
         return 0;
-    return seg_layout(n_total, nseg, c.R, c.NT, c.TM, pairs != 0).total;
+    return seg_layout(n_total, nseg, c.R, c.NT, c.TM, pairs != 0, c.ways).total;
 }
 
 static int run_segmented(const int32_t *kin, const int32_t *vin, int32_t *kout, int32_t *vout,
@@ -664,7 +664,7 @@ static int run_segmented(const int32_t *kin, const int32_t *vin, int32_t *kout, 
     // the merge passes move 16-byte chunks of the output and scratch arrays
     if (((uintptr_t)kout & 15) || (pairs && ((uintptr_t)vout & 15)))
         return HVMS_ERR_INVALID_ARG;
-    st = check_ws(ws, ws_bytes, seg_layout(n_total, nseg, c.R, c.NT, c.TM, pairs).total);
+    st = check_ws(ws, ws_bytes, seg_layout(n_total, nseg, c.R, c.NT, c.TM, pairs, c.ways).total);
     if (st)
         return st;
     const int64_t tile = (int64_t)c.R * c.NT;
@@ -680,7 +680,11 @@ static int run_segmented(const int32_t *kin, const int32_t *vin, int32_t *kout, 
     // all n_total keys would need (passes with no tiles cost a few empty
     // launches)
     const int64_t bound = max_seg < 0 ? n_total : max_seg;
-    a.passes = bound > tile ? ilog2_exact((bound + tile - 1) / tile) : 0;
+    const int levels = bound > tile ? ilog2_exact((bound + tile - 1) / tile) : 0;
+    // four-way: one launch per two merge levels (a segment with an odd
+    // count merges its last level two-way)
+    a.ways = c.ways;
+    a.passes = c.ways == 4 ? (levels + 1) / 2 : levels;
     a.R = c.R;
     a.NT = c.NT;
     a.K = c.K;

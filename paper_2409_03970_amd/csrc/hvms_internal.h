@@ -79,6 +79,14 @@ hipError_t launch_merge4_corank(int tm, bool pairs, const int32_t *kin, const in
 hipError_t launch_merge4_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
                               int32_t *kout, int32_t *vout, int64_t n, int64_t run,
                               const void *rec, int occupancy, hipStream_t s, KeyMap xout = {});
+// segmented four-way pass over the four-way tiles of map (count read from
+// the control block): co-ranks and records from the grid of two-way co-ranks
+// (seg_corank over the same tiles and run), then the merge
+struct SegMap;
+struct CorankCtl;
+hipError_t launch_seg_merge4(int tm, bool pairs, const SegMap &map, int64_t run,
+                             const int64_t *grid, void *rec, int64_t *obase, int64_t max_tiles,
+                             int64_t n_total, const CorankCtl &pc, int occupancy, hipStream_t s);
 hipError_t launch_corank_list(const int32_t *a, int64_t m, const int32_t *b, int64_t k,
                               const int64_t *diag, int64_t count, int64_t *out,
                               const CorankOpts &o, hipStream_t s);
@@ -99,17 +107,20 @@ inline int ceil_log2_host(int64_t x)
 
 // segmented.hip
 struct SegLayout {
-    int64_t ctrl, pieces, fulls, tiles, cr, passes, table, scr_k, scr_v, total, max_tiles,
+    int64_t ctrl, pieces, fulls, tiles, cr, rec, obase, passes, table, scr_k, scr_v, total,
+        max_tiles,
         max_pieces, max_full;
 };
-SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool pairs);
+SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool pairs,
+                     int ways = 2);
 
 struct SegArgs {
     const int32_t *kin, *vin;  // vin == nullptr: keys only
     int32_t *kout, *vout;
     const int64_t *off;
     int64_t nseg, n_total;
-    int passes;                // merge passes the largest segment needs
+    int passes;                // merge launches the largest segment needs
+    int ways;                  // 2: two-way passes; 4: four-way (two levels per launch)
     int R, NT, K, TM, variant, occupancy;
     CorankOpts co;
     void *ws;

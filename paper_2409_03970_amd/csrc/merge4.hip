@@ -303,10 +303,12 @@ struct Tile4 {
 
 // Window geometry of tile g from the co-ranks of its first and next
 // diagonals, clamped so that every window stays inside its run and the four
-// lengths add up to the tile even if the runs were not sorted.
+// lengths add up to the tile even if the runs were not sorted.  abs0: the
+// absolute index of the sequence's first element (a segment's offset; 0 for
+// a whole array), so that chunks are aligned in absolute index.
 template <typename T>
 __device__ __forceinline__ Tile4 tile4_geo(const Group<T> &G, int64_t run, int64_t tm, int64_t g,
-                                           Quad q0, Quad q1)
+                                           Quad q0, Quad q1, int64_t abs0 = 0)
 {
     Tile4 t;
     const int64_t nA = G.X.np, nB = G.X.nq, nC = G.Y.np, nD = G.Y.nq;
@@ -331,8 +333,8 @@ __device__ __forceinline__ Tile4 tile4_geo(const Group<T> &G, int64_t run, int64
     const int64_t c0 = cl(q0.c, y0 > nD ? y0 - nD : 0, y0 < nC ? y0 : nC);
     int64_t c1 = cl(q1.c, y1 > nD ? y1 - nD : 0, y1 < nC ? y1 : nC);
     c1 = cl(c1, c0, c0 + (y1 - y0));
-    const int64_t start[4] = {G.gb + a0, G.gb + run + (x0 - a0), G.gb + 2 * run + c0,
-                              G.gb + 3 * run + (y0 - c0)};
+    const int64_t start[4] = {abs0 + G.gb + a0, abs0 + G.gb + run + (x0 - a0),
+                              abs0 + G.gb + 2 * run + c0, abs0 + G.gb + 3 * run + (y0 - c0)};
     const int64_t len[4] = {a1 - a0, (x1 - a1) - (x0 - a0), c1 - c0, (y1 - c1) - (y0 - c0)};
     t.cnt = (int)(d1 - d0);
     t.nx = (int)(x1 - x0);
@@ -360,12 +362,15 @@ struct TileRec {
     uint32_t w[8];
 };
 
-// The record as the merge kernel holds it (wave-uniform)
+// The record as the merge kernel holds it (wave-uniform); ob: a segmented
+// tile's first output index, with bit 62 set when the segment's data sits
+// in scratch (read scratch, write the output arrays)
 struct TileW {
     int64_t dl[4];
     int cnt, nx;
     int len[4], base[4];
     int c1, c2, c3, nc;
+    int64_t ob;
 };
 static_assert(sizeof(TileRec) == 64, "one 64-byte record per tile");
 
@@ -434,6 +439,66 @@ __global__ __launch_bounds__(64) void quad_corank_kernel(const int32_t *__restri
         out[g] = tile_rec_of(tile4_geo<T>(G, run, tm, g, q, q1));
 }
 
+// The same for the four-way tiles of a segmented pass: tile q of the list is
+// tile j of its segment, whose tiles sit at list positions q - j .. (so the
+// segment's grid entries do too).  Each record's chunk bases are absolute;
+// obase[q] is the tile's first output index, bit 62 marking a segment whose
+// data sits in scratch.
+template <typename T>
+__global__ __launch_bounds__(64) void seg_quad_corank_kernel(SegMap map, int64_t run, int64_t tm,
+                                                              int lg4run,
+                                                              const int64_t *__restrict__ grid,
+                                                              TileRec *__restrict__ out,
+                                                              int64_t *__restrict__ obase,
+                                                              unsigned long long *stats,
+                                                              CorankCtl pc)
+{
+    const int l = threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * 63 + l;
+    const int64_t cnt = map.count();
+    Quad qd{0, 0, 0};
+    Group<T> G{};
+    int64_t base = 0, o0 = 0;
+    int j = 0;
+    bool odd = false;
+    if (q < cnt) {
+        const int2 e = map.entry(q);
+        base = map.off[e.x];
+        const int64_t len = map.off[e.x + 1] - base;
+        j = e.y;
+        odd = ((map.passes[e.x] - map.p) & 1) != 0;
+        const int32_t *ik = odd ? map.scrk : map.outk;
+        const int32_t *iv = odd ? map.scrv : map.outv;
+        o0 = (int64_t)j * tm;
+        G = group_of<T>(ik + base, iv ? iv + base : nullptr, len, run, o0 >> lg4run);
+        const int64_t q0 = q - j;
+        unsigned probes = 0;
+        qd = quad_corank<T>(G, o0 - G.gb, tm, grid, q0 + G.gb / tm, q0 + (G.gb + 2 * run) / tm,
+                            probes, pc.mode != 0 ? &pc : nullptr);
+        if (stats && l < 63) {
+            atomicAdd(stats + 0, 1ull);
+            atomicAdd(stats + 1, (unsigned long long)probes);
+            atomicAdd(stats + 8 + (probes < 63 ? probes : 63), 1ull);
+        }
+    }
+    // the next tile's co-ranks (used only when it is the next tile of the
+    // same group, which is then the next entry of the list)
+    auto next = [&](int64_t v) {
+        const int a = ((l + 1) & 63) << 2;
+        const int lo = __builtin_amdgcn_ds_bpermute(a, (int)(uint32_t)v);
+        const int hi = __builtin_amdgcn_ds_bpermute(a, (int)(v >> 32));
+        return (int64_t)(uint32_t)lo | ((int64_t)hi << 32);
+    };
+    Quad q1;
+    q1.x = next(qd.x);
+    q1.a = next(qd.a);
+    q1.c = next(qd.c);
+    if (l < 63 && q < cnt) {
+        out[q] = tile_rec_of(tile4_geo<T>(G, run, tm, j, qd, q1, base));
+        obase[q] = (base + o0) | ((int64_t)odd << 62);
+    }
+}
+
 // VT consecutive outputs of one thread from registers to absolute index e
 // (a multiple of 4), as 16-byte stores; pairs are split into the key and
 // value arrays, or stored whole when the output is packed (PK).
@@ -460,14 +525,22 @@ __device__ __forceinline__ void store_run(int32_t *__restrict__ k, int32_t *__re
 }
 
 // PK: the output is one packed 64-bit array at kout (the last pass of a
-// 64-bit key sort).
-template <int NT, int VT, typename T, bool PK = false>
+// 64-bit key sort).  SEG: the four-way tiles of a segmented pass: their
+// count is read from *seg_count, and each tile's record comes with its first
+// output index and the side its segment's data sits on (obase): kin/vin are
+// then the output arrays and scrk/scrv the scratch ones, read or written per
+// tile, and a tile whose first output is not 16-byte aligned leaves through
+// LDS with chunk-aligned stores.
+template <int NT, int VT, typename T, bool PK = false, bool SEG = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void merge4_pipe_kernel(const int32_t *__restrict__ kin,
                                                          const int32_t *__restrict__ vin,
                                                          int32_t *__restrict__ kout,
                                                          int32_t *__restrict__ vout, int64_t n,
                                                          int64_t run, const TileRec *__restrict__ rec,
-                                                         int64_t ntiles, int lg4run, KeyMap xout)
+                                                         int64_t ntiles, int lg4run, KeyMap xout,
+                                                         const int64_t *__restrict__ obase,
+                                                         int32_t *scrk, int32_t *scrv,
+                                                         const int64_t *seg_count)
 {
     constexpr int TM = NT * VT;
     constexpr int CH = VT / 4 + 1;  // chunk slots per thread: TM/4 + 6 chunks at most
@@ -479,14 +552,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
     __shared__ __attribute__((aligned(16))) T S[TM + 32 + VT];
     __shared__ __attribute__((aligned(16))) T M[LdsSkew<T>::size(TM + 2 * VT + 8)];
     const int t = threadIdx.x;
-    const int64_t first = blockIdx.x, step = gridDim.x, last = ntiles;
+    const int64_t first = blockIdx.x, step = gridDim.x;
+    const int64_t last = SEG ? *seg_count : ntiles;
     if (first >= last)
         return;
 
     // tile g's record: one 32-bit word per lane 0..15 (a vector load, so
-    // that waiting for it never waits for LDS traffic)
+    // that waiting for it never waits for LDS traffic), and for a segmented
+    // tile its output index in lanes 16 and 17
     const uint32_t *words = (const uint32_t *)rec;
-    auto load_rec = [&](int64_t g) -> uint32_t { return words[g * 16 + (t & 15)]; };
+    auto load_rec = [&](int64_t g) -> uint32_t {
+        if constexpr (SEG) {
+            const int l = t & 31;
+            if (l >= 16)
+                return l < 18 ? ((const uint32_t *)obase)[2 * g + (l & 1)] : 0u;
+        }
+        return words[g * 16 + (t & 15)];
+    };
     auto geo_of = [&](uint32_t rv) {
         auto rl = [&](int lane) { return (uint32_t)__builtin_amdgcn_readlane((int)rv, lane); };
         TileW w;
@@ -509,7 +591,31 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
         w.nc = (int)(c3n >> 16);
         w.cnt = (int)rl(14);
         w.nx = (int)rl(15);
+        w.ob = SEG ? (int64_t)((uint64_t)rl(16) | ((uint64_t)rl(17) << 32)) : 0;
         return w;
+    };
+    // a tile's input and output arrays, and its first output index.  The
+    // choice between two arrays is made in integer arithmetic (a mask):
+    // a select of pointers is turned by the compiler into a table in
+    // scratch memory.
+    auto pick = [](const void *a, const void *b, bool use_b) -> uintptr_t {
+        const uintptr_t m = (uintptr_t)0 - (uintptr_t)use_b;
+        return (uintptr_t)a ^ (((uintptr_t)a ^ (uintptr_t)b) & m);
+    };
+    auto src_k = [=](const TileW &G) -> const int32_t * {
+        return SEG ? (const int32_t *)pick(kin, scrk, (G.ob >> 62) & 1) : kin;
+    };
+    auto src_v = [=](const TileW &G) -> const int32_t * {
+        return SEG ? (const int32_t *)pick(vin, scrv, (G.ob >> 62) & 1) : vin;
+    };
+    auto dst_k = [=](const TileW &G) -> int32_t * {
+        return SEG ? (int32_t *)pick(kout, scrk, !((G.ob >> 62) & 1)) : kout;
+    };
+    auto dst_v = [=](const TileW &G) -> int32_t * {
+        return SEG ? (int32_t *)pick(vout, scrv, !((G.ob >> 62) & 1)) : vout;
+    };
+    auto out0 = [](const TileW &G, int64_t g) -> int64_t {
+        return SEG ? (G.ob & ~((int64_t)1 << 62)) : g * TM;
     };
 
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -529,7 +635,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
                 const int c = t + NT * q;
                 int64_t e = c < nc ? chunk_elem(G, c) : 0;
                 e = (has_tail && e == e_tail) ? e_tail - 4 : e;
-                pf[q] = load_chunk<T>(kin, vin, e);
+                pf[q] = load_chunk<T>(src_k(G), src_v(G), e);
             }
         }
     };
@@ -555,7 +661,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
             const int c = t + NT * q;
             if ((full && q < VT / 4) || c < nc) {
                 if (has_tail && chunk_elem(cur, c) == e_tail)
-                    fix_tail<T>(pf[q], kin, vin, e_tail, n);
+                    fix_tail<T>(pf[q], src_k(cur), src_v(cur), e_tail, n);
                 put_chunk<T>(S, c, pf[q]);
             }
         }
@@ -577,12 +683,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
                         : cur.len[3] == cur.cnt ? cur.base[3]
                                                 : -1;
         if (src >= 0) {
+            const int64_t o = out0(cur, g);
+            const int sh = (int)(o & 3);
             if (full)  // constant count: no end checks
-                copy_run<NT, CH, T, PK>(LdsPlain<T>{S, 0}, src, 0, kout, vout, g * TM,
-                                        TM, t, xout);
+                copy_run<NT, CH, T, PK>(LdsPlain<T>{S, 0}, src, sh, dst_k(cur), dst_v(cur),
+                                        o - sh, TM, t, xout);
             else
-                copy_run<NT, CH, T, PK>(LdsPlain<T>{S, 0}, src, 0, kout, vout, g * TM,
-                                        cur.cnt, t, xout);
+                copy_run<NT, CH, T, PK>(LdsPlain<T>{S, 0}, src, sh, dst_k(cur), dst_v(cur),
+                                        o - sh, cur.cnt, t, xout);
             lds_barrier();  // the next tile's chunks overwrite S
             if (!more)
                 break;
@@ -673,13 +781,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void me
         // before this tile's second barrier) and then, after its first
         // barrier, M.  A ragged tile stages its rows in M (skewed) and
         // copies out the first cnt outputs.
-        if (full) {
-            store_run<VT, T, PK>(kout, vout, g * TM + diag, out);
-        } else {
+        const int64_t o = out0(cur, g);
+        if (full && (o & 3) == 0) {
+            store_run<VT, T, PK>(dst_k(cur), dst_v(cur), o + diag, out);
+        } else if (!SEG) {
             lds_barrier();
             put_row<VT>(MX, diag, out, cur.cnt - diag);
             lds_barrier();
             copy_out<NT, CH, T, PK>(MX, kout, vout, g * TM, cur.cnt, t);
+        } else {  // a segmented tile not aligned to 16 bytes, or ragged
+            lds_barrier();
+            put_row<VT>(MX, diag, out, cur.cnt - diag);
+            lds_barrier();
+            const int sh = (int)(o & 3);
+            copy_run<NT, CH, T, PK>(MX, 0, sh, dst_k(cur), dst_v(cur), o - sh, cur.cnt, t,
+                                    xout);
         }
         if (!more)
             break;
@@ -750,7 +866,7 @@ static hipError_t launch_m4_1(const int32_t *kin, const int32_t *vin, int32_t *k
         grid = ntiles;
     hipLaunchKernelGGL((merge4_pipe_kernel<NT, VT, T, PK>), dim3((unsigned)grid), dim3(NT), 0, s,
                        kin, vin, kout, vout, n, run, (const TileRec *)rec, ntiles, ilog2_pow2(4 * run),
-                       xout);
+                       xout, nullptr, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -804,6 +920,67 @@ hipError_t launch_merge4_pass(int tm, bool pairs, const int32_t *kin, const int3
     case 16384:
         return pairs ? hipErrorInvalidValue
                      : launch_m4<1024, 16, int32_t>(kin, vin, kout, vout, n, run, rec, occupancy, s, xout);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int NT, int VT, typename T>
+static hipError_t launch_m4_seg(const SegMap &map, int64_t n_total, int64_t run, const void *rec,
+                                const int64_t *obase, int64_t max_tiles, int occupancy,
+                                hipStream_t s)
+{
+    int occ = occupancy;
+    if (occ <= 0 &&
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+             &occ, (const void *)merge4_pipe_kernel<NT, VT, T, false, true>, NT, 0) != hipSuccess ||
+         occ <= 0))
+        occ = 1;
+    int64_t grid = (int64_t)device_cus() * occ;
+    if (grid > max_tiles)
+        grid = max_tiles;
+    if (grid < 1)
+        grid = 1;
+    hipLaunchKernelGGL((merge4_pipe_kernel<NT, VT, T, false, true>), dim3((unsigned)grid), dim3(NT),
+                       0, s, map.outk, map.outv, map.outk, map.outv, n_total, run,
+                       (const TileRec *)rec, (int64_t)0, ilog2_pow2(4 * run), KeyMap{}, obase,
+                       map.scrk, map.scrv, map.pass_tiles + map.p);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_merge4(int tm, bool pairs, const SegMap &map, int64_t run,
+                             const int64_t *grid, void *rec, int64_t *obase, int64_t max_tiles,
+                             int64_t n_total, const CorankCtl &pc_in, int occupancy, hipStream_t s)
+{
+    if (!merge4_supported(tm, pairs) || run <= 0 || (run & (run - 1)) != 0 || (2 * run) % tm != 0 ||
+        max_tiles <= 0)
+        return hipErrorInvalidValue;
+    CorankCtl pc = pc_in;
+    pc.stats = nullptr;  // the kernel counts its probes itself
+    pc.pair_cdf = nullptr;
+    pc.pair_first = 0;
+    if (pc.mode == 1 && !pc.table)  // no table: proportional split
+        pc.mode = 2;
+    const unsigned qb = (unsigned)((max_tiles + 62) / 63);
+    const int lg = ilog2_pow2(4 * run);
+    if (pairs)
+        hipLaunchKernelGGL(seg_quad_corank_kernel<int64_t>, dim3(qb), dim3(64), 0, s, map, run,
+                           (int64_t)tm, lg, grid, (TileRec *)rec, obase, pc_in.stats, pc);
+    else
+        hipLaunchKernelGGL(seg_quad_corank_kernel<int32_t>, dim3(qb), dim3(64), 0, s, map, run,
+                           (int64_t)tm, lg, grid, (TileRec *)rec, obase, pc_in.stats, pc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    switch (tm) {
+    case 2048:
+        return launch_m4_seg<256, 8, int64_t>(map, n_total, run, rec, obase, max_tiles, occupancy, s);
+    case 4096:
+        return pairs ? launch_m4_seg<256, 16, int64_t>(map, n_total, run, rec, obase, max_tiles, occupancy, s)
+                     : launch_m4_seg<256, 16, int32_t>(map, n_total, run, rec, obase, max_tiles, occupancy, s);
+    case 8192:
+        return launch_m4_seg<512, 16, int32_t>(map, n_total, run, rec, obase, max_tiles, occupancy, s);
+    case 16384:
+        return launch_m4_seg<1024, 16, int32_t>(map, n_total, run, rec, obase, max_tiles, occupancy, s);
     }
     return hipErrorInvalidValue;
 }

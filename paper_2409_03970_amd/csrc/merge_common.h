@@ -198,17 +198,23 @@ struct PlainMap {
 // Segmented pass p: tile list entries (segment, tile in segment); a
 // segment's data sits in scratch or in the output depending on the parity of
 // the passes it still has to run, so that its last pass writes the output.
+// first_tiles (optional): the pass's tiles start at list position
+// first_tiles[p] (a segmented four-way pass's two-way tiles follow its
+// four-way ones).
 struct SegMap {
     int32_t *outk, *outv, *scrk, *scrv;
     const int64_t *off;
     const int2 *tiles;
     const int32_t *passes;
     const int64_t *pass_tiles;
+    const int64_t *first_tiles;
     int p;
-    __device__ __forceinline__ int64_t count() const { return pass_tiles[p]; }
+    __device__ __forceinline__ int64_t first() const { return first_tiles ? first_tiles[p] : 0; }
+    __device__ __forceinline__ int64_t count() const { return pass_tiles[p] - first(); }
+    __device__ __forceinline__ int2 entry(int64_t q) const { return tiles[q + first()]; }
     __device__ __forceinline__ TileRef at(int64_t q) const
     {
-        const int2 e = tiles[q];
+        const int2 e = entry(q);
         TileRef r;
         r.base = off[e.x];
         r.n = off[e.x + 1] - r.base;

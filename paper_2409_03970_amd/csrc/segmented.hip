@@ -24,7 +24,12 @@
 //               pieces of large segments to output or scratch by the parity
 //               of P_s.
 //  6. passes:   for p < P_max: co-ranks of pass p's tiles, then the
-//               persistent pipelined merge over the same tile list.
+//               persistent pipelined merge over the same tile list.  With
+//               four-way passes a segment takes ceil(L_s / 2) launches for
+//               its L_s merge levels: launch p merges groups of four runs of
+//               TILE * 4^p for the segments with at least two levels left
+//               (the front of pass p's tiles) and pairs of such runs for the
+//               segments with one level left (the rest).
 #include "hvms.h"
 #include "hvms_internal.h"
 #include "merge_common.h"
@@ -54,7 +59,8 @@ enum : int {
     C_TCUR = C_TCNT + kMaxP,        // tile-list cursors per P
     C_TBASE = C_TCUR + kMaxP,       // tile-list base per P
     C_PASS = C_TBASE + kMaxP,       // tiles of pass p
-    C_WORDS = C_PASS + kMaxP
+    C_PASSF = C_PASS + kMaxP,       // four-way passes: the four-way tiles of pass p
+    C_WORDS = C_PASSF + kMaxP
 };
 
 struct Piece {
@@ -76,9 +82,16 @@ struct SegParams {
     int64_t nseg, n_total;
     int64_t max_pieces, max_tiles, max_full;  // list capacities in the workspace
     int tile_log2, r_log2, nb;  // nb = buckets = tile_log2 - r_log2 + 1
-    int passes;                 // merge passes enqueued by the host
+    int passes;                 // merge launches enqueued by the host
+    int ways;                   // 2 or 4 runs merged per launch
     int64_t tm;
 };
+
+// Merge launches of a segment with L merge levels.
+__device__ __forceinline__ int launches_of(const SegParams &P, int L)
+{
+    return P.ways == 4 ? (L + 1) >> 1 : L;
+}
 
 __device__ __forceinline__ int bucket_of(const SegParams &P, int64_t size)
 {
@@ -131,7 +144,7 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned lo
                     atomicAdd(&cnt[bucket_of(P, rest)], 1ull);
                 atomicAdd(&lcnt[ps], 1ull);
                 atomicAdd(&tcnt[ps], (unsigned long long)((size + P.tm - 1) / P.tm));
-                if (ps > P.passes)
+                if (launches_of(P, ps) > P.passes)
                     atomicAdd(&over, 1ull);
             }
         }
@@ -206,14 +219,19 @@ __global__ __launch_bounds__(64) void seg_plan_kernel(SegParams P, unsigned long
         ctrl[C_NTASK] = task;
     }
     if (t < kMaxP) {
-        // tile list ordered by P descending: base of P = t; pass t covers
-        // the segments with P_s > t, a prefix of the list
+        // tile list ordered by merge levels L descending: base of L = t.
+        // Two-way pass t covers the segments with L_s > t, a prefix of the
+        // list; four-way pass p those with L_s > 2p, of which the ones with
+        // L_s > 2p + 1 (four-way tiles) come first
         unsigned long long above = 0;
         for (int q = t + 1; q < kMaxP; ++q)
             above += tcnt[q];
         if (t >= 1)
             ctrl[C_TBASE + t] = above;
-        ctrl[C_PASS + t] = above;
+        if (P.ways == 4)
+            ctrl[((t & 1) ? C_PASSF : C_PASS) + (t >> 1)] = above;
+        else
+            ctrl[C_PASS + t] = above;
     }
 }
 
@@ -258,7 +276,8 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
         // a segment needing more passes than are enqueued runs the enqueued
         // ones (and is counted in C_OVER): its pieces start where that pass
         // count lands them in the output
-        passes[s] = ps < P.passes ? ps : P.passes;
+        const int ls = launches_of(P, ps);
+        passes[s] = ls < P.passes ? ls : P.passes;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
@@ -270,7 +289,8 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
     if (threadIdx.x == 0 && fcnt)
         fbase = atomicAdd(&ctrl[C_FCUR], fcnt);
     __syncthreads();
-    const int dst = ((ps < P.passes ? ps : P.passes) & 1) ? 1 : 0;
+    const int lsd = launches_of(P, ps);
+    const int dst = ((lsd < P.passes ? lsd : P.passes) & 1) ? 1 : 0;
     if (b >= 0 && bbase[b] + mine < (unsigned long long)P.max_pieces) {
         // the segment itself, or the ragged rest after its full pieces
         Piece pc;
@@ -467,7 +487,7 @@ __global__ __launch_bounds__(64) void seg_corank_kernel(SegMap map, int64_t run,
     if (valid) {
         r = map.at(q);
         P = pair_geo(r, tm, run);
-        seg = map.tiles[q].x;
+        seg = map.entry(q).x;
         pb = P.pb;
     }
     const int prev = (lane + 63) & 63;
@@ -523,7 +543,7 @@ hipError_t launch_seg_status(const void *ws, int64_t *out, hipStream_t s)
     return hipGetLastError();
 }
 
-SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool pairs)
+SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool pairs, int ways)
 {
     SegLayout L{};
     const int64_t tile = (int64_t)R * NT;
@@ -541,6 +561,12 @@ SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool 
     o += a256(max_tiles * 8);
     L.cr = o;
     o += a256((max_tiles + 1) * 8);
+    if (ways == 4) {  // four-way tiles: a window-geometry record and an output index each
+        L.rec = o;
+        o += a256((max_tiles + 1) * (int64_t)merge4_record_bytes());
+        L.obase = o;
+        o += a256((max_tiles + 1) * 8);
+    }
     L.passes = o;
     o += a256(nseg * 4);
     L.table = o;  // the learned co-rank's model table (used in learned mode)
@@ -669,7 +695,7 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
     const bool pairs = a.vin != nullptr;
     const int64_t tile = (int64_t)a.R * a.NT;
     const int tile_log2 = ceil_log2_host(tile), r_log2 = ceil_log2_host(a.R);
-    const SegLayout L = seg_layout(a.n_total, a.nseg, a.R, a.NT, a.TM, pairs);
+    const SegLayout L = seg_layout(a.n_total, a.nseg, a.R, a.NT, a.TM, pairs, a.ways);
     SegParams P;
     P.off = a.off;
     P.nseg = a.nseg;
@@ -681,6 +707,7 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
     P.r_log2 = r_log2;
     P.nb = tile_log2 - r_log2 + 1;
     P.passes = a.passes;
+    P.ways = a.ways;
     P.tm = a.TM;
     char *ws = (char *)a.ws;
     unsigned long long *ctrl = (unsigned long long *)(ws + L.ctrl);
@@ -715,6 +742,37 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
             return e;
     }
 
+    // co-ranks then merge over the two-way tiles of a map (run: the runs it
+    // merges in pairs)
+    auto two_way = [&](const SegMap &map, int64_t run, const CorankCtl &c) -> hipError_t {
+        const unsigned cb = (unsigned)((L.max_tiles + 63) / 64);
+        if (pairs)
+            hipLaunchKernelGGL(seg_corank_kernel<int64_t>, dim3(cb), dim3(64), 0, s, map, run,
+                               (int64_t)a.TM, cr, c);
+        else
+            hipLaunchKernelGGL(seg_corank_kernel<int32_t>, dim3(cb), dim3(64), 0, s, map, run,
+                               (int64_t)a.TM, cr, c);
+        hipError_t e2 = hipGetLastError();
+        if (e2 != hipSuccess)
+            return e2;
+        const bool xcd = a.variant == 3;
+        switch (a.TM) {
+        case 2048:
+            return pairs ? launch_seg_merge<256, 8, int64_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s)
+                         : launch_seg_merge<256, 8, int32_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s);
+        case 4096:
+            return pairs ? launch_seg_merge<256, 16, int64_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s)
+                         : launch_seg_merge<256, 16, int32_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s);
+        case 8192:
+            return pairs ? launch_seg_merge<512, 16, int64_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s)
+                         : launch_seg_merge<512, 16, int32_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s);
+        case 16384:
+            return pairs ? hipErrorInvalidValue
+                         : launch_seg_merge<512, 32, int32_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s);
+        }
+        return hipErrorInvalidValue;
+    };
+
     for (int p = 0; p < a.passes; ++p) {
         SegMap map;
         map.outk = a.kout;
@@ -725,8 +783,8 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
         map.tiles = tiles;
         map.passes = passes;
         map.pass_tiles = (const int64_t *)(ctrl + C_PASS);
+        map.first_tiles = nullptr;
         map.p = p;
-        const int64_t run = tile << p;
         CorankCtl c;
         c.mode = a.co.mode;
         c.radius_log2 = a.co.radius_log2;
@@ -735,37 +793,35 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
         c.pair_cdf = nullptr;
         c.pair_first = 0;
         c.table = a.co.mode == HVMS_CORANK_LEARNED ? table : nullptr;
+        if (a.ways != 4) {
+            e = two_way(map, tile << p, c);
+            if (e != hipSuccess)
+                return e;
+            continue;
+        }
+        // four-way launch p: runs of TILE * 4^p; first the four-way tiles
+        // (the grid of two-way co-ranks, then the four-way co-ranks and the
+        // merge), then the two-way tiles of the segments with one level left
+        const int64_t run = tile << (2 * p);
+        SegMap m4 = map;
+        m4.pass_tiles = (const int64_t *)(ctrl + C_PASSF);
         const unsigned cb = (unsigned)((L.max_tiles + 63) / 64);
         if (pairs)
-            hipLaunchKernelGGL(seg_corank_kernel<int64_t>, dim3(cb), dim3(64), 0, s, map, run,
+            hipLaunchKernelGGL(seg_corank_kernel<int64_t>, dim3(cb), dim3(64), 0, s, m4, run,
                                (int64_t)a.TM, cr, c);
         else
-            hipLaunchKernelGGL(seg_corank_kernel<int32_t>, dim3(cb), dim3(64), 0, s, map, run,
+            hipLaunchKernelGGL(seg_corank_kernel<int32_t>, dim3(cb), dim3(64), 0, s, m4, run,
                                (int64_t)a.TM, cr, c);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;
-        const bool xcd = a.variant == 3;
-        switch (a.TM) {
-        case 2048:
-            e = pairs ? launch_seg_merge<256, 8, int64_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s)
-                      : launch_seg_merge<256, 8, int32_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s);
-            break;
-        case 4096:
-            e = pairs ? launch_seg_merge<256, 16, int64_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s)
-                      : launch_seg_merge<256, 16, int32_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s);
-            break;
-        case 8192:
-            e = pairs ? launch_seg_merge<512, 16, int64_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s)
-                      : launch_seg_merge<512, 16, int32_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s);
-            break;
-        case 16384:
-            e = pairs ? hipErrorInvalidValue
-                      : launch_seg_merge<512, 32, int32_t>(map, run, cr, a.n_total, L.max_tiles, a.occupancy, xcd, s);
-            break;
-        default:
-            e = hipErrorInvalidValue;
-        }
+        e = launch_seg_merge4(a.TM, pairs, m4, run, cr, ws + L.rec, (int64_t *)(ws + L.obase),
+                              L.max_tiles, a.n_total, c, a.occupancy, s);
+        if (e != hipSuccess)
+            return e;
+        SegMap m2 = map;
+        m2.first_tiles = (const int64_t *)(ctrl + C_PASSF);
+        e = two_way(m2, run, c);
         if (e != hipSuccess)
             return e;
     }

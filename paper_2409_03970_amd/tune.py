@@ -75,7 +75,9 @@ def candidates(op):
             continue
         if op != "sort" and R * NT * 8 > 163840:
             continue
-        if W == 4 and (op == "segmented" or V == 3 or (op == "sort_pairs" and TM != 4096)):
+        if W == 4 and (V == 3 or (op in ("sort_pairs", "segmented_pairs") and TM != 4096)):
+            continue
+        if op == "segmented_pairs" and (R, NT) == (16, 1024):  # pair tile + piece table > LDS
             continue
         out.append(dict(keys_per_lane=R, block_threads=NT, wave_levels=K + 1, merge_tile=TM,
                         merge_variant=V, merge_ways=W))
@@ -96,29 +98,44 @@ def _time(fn, reps):
 
 
 def tune(op="sort", log2n=24, nseg=200000, seg_max=65536, reps=5, seed=0, path=CACHE,
-         cands=None, verbose=True, dists=("uniform",)):
+         cands=None, verbose=True, dists=("uniform",), seg_min=1):
     """Times every candidate (and the defaults) on the operation's workload
-    and records the fastest in the cache.  dists (sort / sort_pairs): the key
+    and records the fastest in the cache.  Segmented ops: nseg segments of
+    sizes log-uniform in [seg_min, seg_max].  dists (sort / sort_pairs): the key
     distributions the objective sums over, each a separate input of 2^log2n
     keys; every candidate must reproduce the defaults' outputs exactly."""
     import paper_2409_03970_amd as hv
     from paper_2409_03970_amd import inputs
     dev = torch.device("cuda", torch.cuda.current_device())
-    if op == "segmented":
-        sizes = inputs.log_uniform_sizes(nseg, 1, seg_max, seed=seed)
+    if op in ("segmented", "segmented_pairs"):
+        pairs = op == "segmented_pairs"
+        sizes = inputs.log_uniform_sizes(nseg, seg_min, seg_max, seed=seed)
         offs = inputs.offsets_from_sizes(sizes)
         n = int(offs[-1])
         d_off = offs.to(dev)
         max_seg = int(sizes.max())
-        keys = inputs.keys(n, "uniform", seed=seed, device=dev)
+        if tuple(dists) == ("uniform",):
+            keys = inputs.keys(n, "uniform", seed=seed, device=dev)
+            seg_id = torch.repeat_interleave(torch.arange(nseg, device=dev), sizes.to(dev))
+            vals = (torch.arange(n, device=dev) - offs.to(dev)[seg_id]).to(torch.int32)
+        else:  # each segment drawn from one of the given distributions
+            pick = inputs.segment_distributions(nseg, seed=seed)
+            idx = torch.tensor([inputs.DISTRIBUTIONS.index(d) for d in dists])
+            keys, vals = inputs.segment_pairs(sizes, idx[pick % len(dists)], seed=seed,
+                                              device=dev)
         out = torch.empty_like(keys)
+        if pairs:  # each segment's values: the index inside the segment
+            vout = torch.empty_like(vals)
 
         def run(o):
             ws = hv._workspace(hv.lib().hvms_segmented_workspace_bytes(
-                n, nseg, max_seg, 0, hv._opts(o)), dev)
+                n, nseg, max_seg, int(pairs), hv._opts(o)), dev)
+            if pairs:
+                return lambda: hv.hvms_segmented_sort_pairs_i32(keys, vals, out, vout, d_off, n,
+                                                                max_seg, ws, opts=o)
             return lambda: hv.hvms_segmented_sort_i32(keys, out, d_off, n, max_seg, ws, opts=o)
         log2n = int(round(math.log2(n)))
-        outputs = (out,)
+        outputs = (out, vout) if pairs else (out,)
     elif op in ("sort", "sort_pairs"):
         n = 1 << log2n
         keyset = [inputs.keys(n, d, seed=seed, device=dev) for d in dists]
@@ -163,8 +180,9 @@ def tune(op="sort", log2n=24, nseg=200000, seg_max=65536, reps=5, seed=0, path=C
     cache = load_cache(path)
     entry = {"options": best, "ms": best_ms, "default_ms": base_ms, "n": n,
              "candidates": len(results)}
-    if op != "segmented":
-        entry["dists"] = list(dists)
+    entry["dists"] = list(dists)
+    if op in ("segmented", "segmented_pairs"):
+        entry["segments"] = [nseg, seg_min, seg_max]
     # the best configuration with two-way passes only, for comparison
     two = next((r for r in results if r[1].get("merge_ways", 2) == 2), None)
     if two is not None:
@@ -180,9 +198,11 @@ def tune(op="sort", log2n=24, nseg=200000, seg_max=65536, reps=5, seed=0, path=C
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--op", default="sort", choices=["sort", "sort_pairs", "segmented"])
+    ap.add_argument("--op", default="sort",
+                    choices=["sort", "sort_pairs", "segmented", "segmented_pairs"])
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--nseg", type=int, default=200000)
+    ap.add_argument("--seg-min", type=int, default=1)
     ap.add_argument("--seg-max", type=int, default=65536)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--dists", default="uniform",
@@ -190,7 +210,8 @@ def main():
                          "(sort / sort_pairs), e.g. uniform,gaussian,sorted,reverse,distinct16,zipf")
     ap.add_argument("--path", default=CACHE, help="tuning cache to update (default: the package's)")
     a = ap.parse_args()
-    tune(a.op, a.log2n, a.nseg, a.seg_max, a.reps, path=a.path, dists=tuple(a.dists.split(",")))
+    tune(a.op, a.log2n, a.nseg, a.seg_max, a.reps, path=a.path, dists=tuple(a.dists.split(",")),
+         seg_min=a.seg_min)
 
 
 if __name__ == "__main__":

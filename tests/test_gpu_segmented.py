@@ -378,3 +378,116 @@ def test_learned_corank_segments_match_oracle(pairs):
         assert torch.equal(y, hv.segmented_sort(k, offs))
     s = hv.corank_stats(st.cpu())
     assert s["coranks"] > 0 and s.get("predicted", 0) > 0
+
+
+# ------------------------------------------------ four-way segmented passes
+
+_FOUR = [dict(keys_per_lane=R, block_threads=NT, merge_tile=TM, merge_ways=4, merge_variant=V)
+         for R, NT in [(16, 256), (16, 512), (8, 512), (32, 256), (32, 512)]
+         for TM in (4096, 8192, 16384) if TM <= 2 * R * NT
+         for V in (0, 2)]
+
+
+@pytest.mark.parametrize("opt", _FOUR, ids=lambda o: "R{keys_per_lane}_NT{block_threads}_TM{merge_tile}_V{merge_variant}".format(**o))
+def test_four_way_every_shape(opt):
+    # segments of one to about 2^19 keys: up to five merge levels, both
+    # parities (an odd count ends with a two-way level), segment offsets at
+    # every alignment
+    _say("segmented four-way", opt)
+    _run(inputs.log_uniform_sizes(400, 1, 1 << 19, seed=41), seed=41, opts=opt)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "sorted", "reverse", "distinct16", "zipf"])
+def test_four_way_distributions(dist):
+    _run(inputs.log_uniform_sizes(300, 1, 300000, seed=42), dist=dist, seed=42,
+         opts={"merge_ways": 4, "merge_tile": 4096})
+
+
+def test_four_way_edge_sizes():
+    # around the tile, two, four and eight tiles, and single segments whose
+    # level counts are odd and even
+    opts = {"keys_per_lane": 8, "block_threads": 256, "merge_tile": 4096, "merge_ways": 4}
+    t = 2048
+    sizes = [0, 1, t - 1, t, t + 1, 2 * t, 2 * t + 1, 4 * t - 3, 4 * t, 4 * t + 1, 8 * t, 8 * t + 5,
+             16 * t - 1, 16 * t, 16 * t + 1, 0, 33 * t + 7, 3, 64 * t, 129 * t + 1]
+    _run(sizes, seed=43, opts=opts)
+    _run(sizes[::-1], dist="distinct16", seed=44, opts=opts)
+    _run([200003], seed=45, opts=opts)
+
+
+@pytest.mark.parametrize("tm", [2048, 4096])
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "sorted"])
+def test_four_way_pairs(tm, dist):
+    _run(inputs.log_uniform_sizes(300, 1, 200000, seed=46), dist=dist, seed=46, pairs=True,
+         opts={"keys_per_lane": 16, "block_threads": 256, "merge_tile": tm, "merge_ways": 4})
+
+
+def test_four_way_graph_capture_replays():
+    sizes = inputs.log_uniform_sizes(2000, 1, 100000, seed=47)
+    offs = inputs.offsets_from_sizes(sizes)
+    n = int(offs[-1])
+    k = inputs.keys(n, "uniform", seed=47, device=DEV)
+    d_off = offs.to(DEV)
+    opts = {"merge_ways": 4, "merge_tile": 4096}
+    ws = torch.empty(hv.lib().hvms_segmented_workspace_bytes(n, sizes.numel(), int(sizes.max()),
+                                                             0, hv._opts(opts)),
+                     dtype=torch.uint8, device=DEV)
+    out = torch.empty_like(k)
+    want = oracle.segmented_sort(k.cpu().numpy(), offs.numpy())
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            hv.hvms_segmented_sort_i32(k, out, d_off, n, int(sizes.max()), ws, opts=opts)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), want), rep
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_four_way_max_seg_underestimated(pairs):
+    # max_seg = 4096 over 2048-key tiles: one merge level, so one launch;
+    # a four-way launch merges two levels, so segments up to 8192 keys are
+    # sorted and longer ones are left as sorted runs of 8192 and counted
+    sizes = torch.tensor(_SIZES, dtype=torch.int64)
+    offs = inputs.offsets_from_sizes(sizes)
+    n = int(offs[-1])
+    k = inputs.keys(n, "uniform", seed=48, device=DEV)
+    v = torch.arange(n, dtype=torch.int32, device=DEV) if pairs else None
+    opts = dict(_SMALL, merge_tile=4096, merge_ways=4)
+    out, vo, st = _raw_segmented(k, offs, 4096, opts, vals=v)
+    assert st == [int((sizes > 8192).sum()), 0, 0]
+    kh, got = k.cpu().numpy(), out.cpu().numpy()
+    vh = v.cpu().numpy() if pairs else None
+    gotv = vo.cpu().numpy() if pairs else None
+    o = offs.tolist()
+    for s in range(len(_SIZES)):
+        run = 8192 if _SIZES[s] > 8192 else max(_SIZES[s], 1)
+        for a in range(o[s], o[s + 1], run):
+            b = min(a + run, o[s + 1])
+            if pairs:
+                ek, ev = oracle.sort_pairs(kh[a:b], vh[a:b])
+                assert np.array_equal(got[a:b], ek) and np.array_equal(gotv[a:b], ev), (s, a)
+            else:
+                assert np.array_equal(got[a:b], oracle.sort(kh[a:b])), (s, a)
+
+
+def test_four_way_learned_corank_segments():
+    sizes = inputs.log_uniform_sizes(200, 1, 400000, seed=49)
+    offs = inputs.offsets_from_sizes(sizes)
+    n = int(offs[-1])
+    k = inputs.keys(n, "mixture", seed=49, device=DEV)
+    params = hv.fit_cdf_model(k, frac=0.02, steps=150, batch=8192, lr=3e-3, seed=49)
+    st = torch.zeros(hv.STATS_WORDS, dtype=torch.int64, device=DEV)
+    opts = {"corank_mode": hv.CORANK_LEARNED, "cdf_params": params, "radius_log2": 9,
+            "stats": st, "merge_ways": 4, "merge_tile": 4096}
+    y = hv.segmented_sort(k, offs, opts=opts)
+    assert np.array_equal(y.cpu().numpy(), oracle.segmented_sort(k.cpu().numpy(), offs.numpy()))
+    assert torch.equal(y, hv.segmented_sort(k, offs, opts={"merge_ways": 4, "merge_tile": 4096}))
+    s = hv.corank_stats(st.cpu())
+    assert s["coranks"] > 0 and s.get("predicted", 0) > 0
