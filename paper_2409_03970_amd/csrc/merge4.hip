@@ -24,12 +24,46 @@ namespace hvms {
 
 namespace {
 
+// An element of a key-value run as the co-rank searches handle it: the key
+// is read, the value only when a comparison ties on the key (the order of
+// pack_pair: both words signed), so a probe reads 4 bytes per run, not 8.
+struct KeyRef {
+    int32_t key;
+    const int32_t *v;
+    int64_t i;
+};
+__device__ __forceinline__ bool operator<(const KeyRef &x, const KeyRef &y)
+{
+    if (x.key != y.key)
+        return x.key < y.key;
+    return x.v[x.i] < y.v[y.i];
+}
+template <typename T> struct VElem {
+    using type = T;
+};
+template <> struct VElem<int64_t> {
+    using type = KeyRef;
+};
+
 // One virtual run V = P (+) Q of two sorted arrays (P first on ties).
 template <typename T> struct VRun {
+    using E = typename VElem<T>::type;
     const int32_t *pk, *pv, *qk, *qv;
     int64_t np, nq;
-    __device__ __forceinline__ T P(int64_t i) const { return load_elem<T>(pk, pv, i); }
-    __device__ __forceinline__ T Q(int64_t i) const { return load_elem<T>(qk, qv, i); }
+    __device__ __forceinline__ E P(int64_t i) const
+    {
+        if constexpr (sizeof(T) == 8)
+            return KeyRef{pk[i], pv, i};
+        else
+            return pk[i];
+    }
+    __device__ __forceinline__ E Q(int64_t i) const
+    {
+        if constexpr (sizeof(T) == 8)
+            return KeyRef{qk[i], qv, i};
+        else
+            return qk[i];
+    }
     __device__ __forceinline__ int64_t len() const { return np + nq; }
 
     // co-rank of diagonal k, known to lie in [lo, hi]
@@ -51,22 +85,31 @@ template <typename T> struct VRun {
     }
     // element at output k (k < len) given i = co-rank(k); fromP tells which
     // operand it came from (then co-rank(k + 1) = i + fromP)
-    __device__ __forceinline__ T at(int64_t k, int64_t i, bool &fromP) const
+    __device__ __forceinline__ E at(int64_t k, int64_t i, bool &fromP) const
     {
         const int64_t j = k - i;
-        fromP = i < np && (j >= nq || !(Q(j) < P(i)));
-        return fromP ? P(i) : Q(j);
+        if (i >= np) {
+            fromP = false;
+            return Q(j);
+        }
+        if (j >= nq) {
+            fromP = true;
+            return P(i);
+        }
+        const E a = P(i), b = Q(j);
+        fromP = !(b < a);
+        return fromP ? a : b;
     }
     // element at output k - 1 (k >= 1) given i = co-rank(k): the larger of
     // the last taken elements (Q's wins ties, it is merged after P's)
-    __device__ __forceinline__ T last(int64_t k, int64_t i) const
+    __device__ __forceinline__ E last(int64_t k, int64_t i) const
     {
         const int64_t j = k - i;
         if (i == 0)
             return Q(j - 1);
         if (j == 0)
             return P(i - 1);
-        const T a = P(i - 1), b = Q(j - 1);
+        const E a = P(i - 1), b = Q(j - 1);
         return b < a ? a : b;
     }
 };
@@ -128,7 +171,7 @@ __device__ __forceinline__ void rank2(const VRun<T> &X, int64_t kx, int64_t lx, 
     while (lx < hx || ly < hy) {
         const bool sx = lx < hx, sy = ly < hy;
         const int64_t mx = lx + ((hx - lx) >> 1), my = ly + ((hy - ly) >> 1);
-        T px, qx, py, qy;
+        typename VRun<T>::E px{}, qx{}, py{}, qy{};
         if (sx) {
             px = X.P(mx);
             qx = X.Q(kx - 1 - mx);
@@ -274,8 +317,8 @@ __device__ Quad quad_corank(const Group<T> &G, int64_t d, int64_t tm, const int6
                  am, Y, y, cL > y - (d - lo) + cH ? cL : y - (d - lo) + cH,
                  cH < y - (d - hi) + cL ? cH : y - (d - hi) + cL, ym, probes);
         bool fx, fy;
-        const T xv = X.at(mid, am, fx);
-        const T yv = Y.at(y, ym, fy);
+        const auto xv = X.at(mid, am, fx);
+        const auto yv = Y.at(y, ym, fy);
         if (yv < xv) {  // X[mid] comes after Y[d-1-mid]: x <= mid
             hi = mid;
             aH = am;
