@@ -349,10 +349,10 @@ def _mode_stats(x, out, ws, opts, params, mode, radius=12):
 
 
 def corank_modes(xs, dists, out, ws, opts, opts4=None, ws4=None):
-    """Binary vs learned vs linear co-rank on the same 2^28 inputs: in the
-    best two-way shape (the two-way co-rank is the one the model predicts)
-    and, with opts4, in the tuned four-way shape (where the prediction picks
-    the grid interval of each tile's splitter)."""
+    """Binary vs learned vs linear co-rank on the same 2^28 inputs in the
+    best two-way shape (the two-way co-rank is the one the model predicts),
+    and with opts4 the co-rank time of the tuned four-way shape, whose
+    co-ranks are selected in the runs directly in every mode."""
     res = {}
     for x, d in zip(xs, dists):
         t0 = torch.cuda.Event(enable_timing=True)
@@ -366,10 +366,7 @@ def corank_modes(xs, dists, out, ws, opts, opts4=None, ws4=None):
                            ("linear", hv.CORANK_LINEAR)):
             r[name] = _mode_stats(x, out, ws, opts, params, mode)
         if opts4 is not None:
-            r["four_way"] = {name: _mode_stats(x, out, ws4, opts4, params, mode)
-                             for name, mode in (("binary", hv.CORANK_BINARY),
-                                                ("learned", hv.CORANK_LEARNED),
-                                                ("linear", hv.CORANK_LINEAR))}
+            r["four_way"] = _mode_stats(x, out, ws4, opts4, params, hv.CORANK_BINARY)
         res[d] = r
     return res
 
@@ -523,8 +520,8 @@ def learned_bench():
                             res["linear"]["output_equals_binary"])
     res["options"] = opts
     # the same modes in the best two-way shape, where every co-rank of a
-    # pass is a predicted two-way co-rank (in the four-way shape the model
-    # also picks each tile's grid interval)
+    # pass is a predicted two-way co-rank (the tuned four-way shape selects
+    # its co-ranks in the runs directly, so there the modes coincide)
     o2 = tune.tuned_options("sort", n, two_way=True)
     if o2 and o2.get("merge_ways", 2) == 2 and o2 != opts:
         ws2 = hv._workspace(hv.lib().hvms_sort_workspace_bytes(n, 0, hv._opts(o2)), dev)

@@ -44,7 +44,8 @@ enum {
     HVMS_ERR_TOO_LARGE = -5    /* input beyond a fixed-size entry point's limit */
 };
 
-/* Co-rank search modes for the global merge passes. */
+/* Co-rank search modes for the two-way merge passes (a four-way pass
+ * selects its co-ranks in the four runs directly, in every mode). */
 enum {
     HVMS_CORANK_BINARY = 0,  /* plain binary search on the merge path          */
     HVMS_CORANK_LEARNED = 1, /* CDF-model prediction + exact bounded search     */
@@ -111,7 +112,8 @@ typedef struct hvms_options {
 
 enum {
     HVMS_STAT_CORANKS = 0,   /* co-ranks computed                            */
-    HVMS_STAT_PROBES = 1,    /* dependent probe pairs read from memory       */
+    HVMS_STAT_PROBES = 1,    /* dependent probe pairs read from memory (a
+                              * four-way co-rank: its rounds of reads)      */
     HVMS_STAT_FALLBACKS = 2, /* bounded searches that fell back to binary    */
     HVMS_STAT_ABS_ERR = 3,   /* sum of |prediction - co-rank|                */
     HVMS_STAT_MAX_ERR = 4,   /* max |prediction - co-rank|                   */

@@ -201,8 +201,8 @@ int run_sort(bool pairs, const int32_t *kin, const int32_t *vin, int32_t *kout, 
             ov = km.packed ? nullptr : vout;
         }
         if (p >= P2) {
-            st = hip_status(launch_merge4_corank(c.TM, pairs, dk, dv, n, run, cr,
-                                                 base + w.records, co, s));
+            st = hip_status(launch_merge4_corank(c.TM, pairs, dk, dv, n, run, base + w.records,
+                                                 co, s));
             if (st)
                 return st;
             trace(c, 2 + 2 * p, s);

@@ -68,25 +68,23 @@ hipError_t launch_merge_pass(int tm, bool pairs, const int32_t *kin, const int32
                              KeyMap xout = {});
 int device_cus();
 
-// merge4.hip: four-way passes (sample grid of two-way co-ranks, co-rank
-// records, pipelined merge); grid: one int64 per tile, rec: one record per
-// tile (merge4_record_bytes), both with room for two more
+// merge4.hip: four-way passes (co-rank records by selection in the four
+// runs of each group, pipelined merge); rec: one record per tile
+// (merge4_record_bytes) with room for two more
 bool merge4_supported(int tm, bool pairs);
 size_t merge4_record_bytes();
 hipError_t launch_merge4_corank(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
-                                int64_t n, int64_t run, int64_t *grid, void *rec,
-                                const CorankOpts &o, hipStream_t s);
+                                int64_t n, int64_t run, void *rec, const CorankOpts &o,
+                                hipStream_t s);
 hipError_t launch_merge4_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
                               int32_t *kout, int32_t *vout, int64_t n, int64_t run,
                               const void *rec, int occupancy, hipStream_t s, KeyMap xout = {});
 // segmented four-way pass over the four-way tiles of map (count read from
-// the control block): co-ranks and records from the grid of two-way co-ranks
-// (seg_corank over the same tiles and run), then the merge
+// the control block): co-ranks and records, then the merge
 struct SegMap;
-struct CorankCtl;
-hipError_t launch_seg_merge4(int tm, bool pairs, const SegMap &map, int64_t run,
-                             const int64_t *grid, void *rec, int64_t *obase, int64_t max_tiles,
-                             int64_t n_total, const CorankCtl &pc, int occupancy, hipStream_t s);
+hipError_t launch_seg_merge4(int tm, bool pairs, const SegMap &map, int64_t run, void *rec,
+                             int64_t *obase, int64_t max_tiles, int64_t n_total,
+                             unsigned long long *stats, int occupancy, hipStream_t s);
 hipError_t launch_corank_list(const int32_t *a, int64_t m, const int32_t *b, int64_t k,
                               const int64_t *diag, int64_t count, int64_t *out,
                               const CorankOpts &o, hipStream_t s);

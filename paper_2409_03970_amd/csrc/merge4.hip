@@ -6,11 +6,12 @@
 // Output tile g covers [g*TM, (g+1)*TM) of its group.  Its windows follow from
 // three co-ranks of its first diagonal d: x = number of X = A(+)B elements
 // among the first d outputs of X (+) Y (Y = C(+)D), a = co-rank of x in A(+)B,
-// c = co-rank of d - x in C(+)D.  X and Y are never stored.  The two-way
-// co-ranks of every tile-aligned diagonal of X and of Y (one launch of the
-// two-way co-rank kernel) form a sample grid that confines x to one interval
-// of TM diagonals; a nested bisection finishes inside it.  The co-rank
-// kernel turns the co-ranks of a tile's first and next diagonals into the
+// c = co-rank of d - x in C(+)D.  X and Y are never stored.  The three
+// follow from the shares of A, B, C and D among the group's d smallest
+// elements, which the co-rank kernel selects in the four runs directly
+// (select4: one round of independent reads per halving of a stride, no
+// nested searches).  The co-rank kernel turns the co-ranks of a tile's
+// first and next diagonals into the
 // tile's window geometry, one 64-byte record per tile, so that the merge
 // kernel's waves do no 64-bit geometry arithmetic of their own.  The merge
 // kernel loads the four windows (TM elements together), merges A with B and
@@ -24,94 +25,10 @@ namespace hvms {
 
 namespace {
 
-// An element of a key-value run as the co-rank searches handle it: the key
-// is read, the value only when a comparison ties on the key (the order of
-// pack_pair: both words signed), so a probe reads 4 bytes per run, not 8.
-struct KeyRef {
-    int32_t key;
-    const int32_t *v;
-    int64_t i;
-};
-__device__ __forceinline__ bool operator<(const KeyRef &x, const KeyRef &y)
-{
-    if (x.key != y.key)
-        return x.key < y.key;
-    return x.v[x.i] < y.v[y.i];
-}
-template <typename T> struct VElem {
-    using type = T;
-};
-template <> struct VElem<int64_t> {
-    using type = KeyRef;
-};
-
 // One virtual run V = P (+) Q of two sorted arrays (P first on ties).
-template <typename T> struct VRun {
-    using E = typename VElem<T>::type;
+struct VRun {
     const int32_t *pk, *pv, *qk, *qv;
     int64_t np, nq;
-    __device__ __forceinline__ E P(int64_t i) const
-    {
-        if constexpr (sizeof(T) == 8)
-            return KeyRef{pk[i], pv, i};
-        else
-            return pk[i];
-    }
-    __device__ __forceinline__ E Q(int64_t i) const
-    {
-        if constexpr (sizeof(T) == 8)
-            return KeyRef{qk[i], qv, i};
-        else
-            return qk[i];
-    }
-    __device__ __forceinline__ int64_t len() const { return np + nq; }
-
-    // co-rank of diagonal k, known to lie in [lo, hi]
-    __device__ __forceinline__ int64_t rank(int64_t k, int64_t lo, int64_t hi,
-                                            unsigned &probes) const
-    {
-        const int64_t flo = k > nq ? k - nq : 0, fhi = k < np ? k : np;
-        lo = lo < flo ? flo : (lo > fhi ? fhi : lo);
-        hi = hi > fhi ? fhi : (hi < lo ? lo : hi);
-        while (lo < hi) {
-            const int64_t mid = lo + ((hi - lo) >> 1);
-            ++probes;
-            if (Q(k - 1 - mid) < P(mid))
-                hi = mid;
-            else
-                lo = mid + 1;
-        }
-        return lo;
-    }
-    // element at output k (k < len) given i = co-rank(k); fromP tells which
-    // operand it came from (then co-rank(k + 1) = i + fromP)
-    __device__ __forceinline__ E at(int64_t k, int64_t i, bool &fromP) const
-    {
-        const int64_t j = k - i;
-        if (i >= np) {
-            fromP = false;
-            return Q(j);
-        }
-        if (j >= nq) {
-            fromP = true;
-            return P(i);
-        }
-        const E a = P(i), b = Q(j);
-        fromP = !(b < a);
-        return fromP ? a : b;
-    }
-    // element at output k - 1 (k >= 1) given i = co-rank(k): the larger of
-    // the last taken elements (Q's wins ties, it is merged after P's)
-    __device__ __forceinline__ E last(int64_t k, int64_t i) const
-    {
-        const int64_t j = k - i;
-        if (i == 0)
-            return Q(j - 1);
-        if (j == 0)
-            return P(i - 1);
-        const E a = P(i - 1), b = Q(j - 1);
-        return b < a ? a : b;
-    }
 };
 
 struct Quad {
@@ -119,7 +36,7 @@ struct Quad {
 };
 
 template <typename T> struct Group {
-    VRun<T> X, Y;
+    VRun X, Y;
     int64_t gb;  // absolute index of the group's first element
 };
 
@@ -151,189 +68,196 @@ __device__ __forceinline__ Group<T> group_of(const int32_t *k, const int32_t *v,
     return G;
 }
 
-// Two independent bounded co-rank searches (one in X, one in Y), stepped
-// together so that the loads of both are in flight at once.
-template <typename T>
-__device__ __forceinline__ void rank2(const VRun<T> &X, int64_t kx, int64_t lx, int64_t hx,
-                                      int64_t &rx, const VRun<T> &Y, int64_t ky, int64_t ly,
-                                      int64_t hy, int64_t &ry, unsigned &probes)
+// Selection among four windows of the runs A, B, C, D (window r holds the
+// elements [0, W_r) of its run from some base on): how many elements of each
+// window are among the D smallest of their union, in the order of the
+// four-way merge, (key, run) for keys and (key, value, run) for pairs.  Past
+// its end a window reads as a sentinel, after every element, sentinels of
+// different windows ordered by r.  Keys become one 64-bit word
+// (key << 2 | r); a pair keeps its key, run and a pointer to its value, read
+// only when two keys tie.
+template <typename T> struct SelE;
+template <> struct SelE<int32_t> {
+    int64_t w;
+};
+template <> struct SelE<int64_t> {
+    int32_t key, r;
+    const int32_t *vp;  // nullptr: the sentinel
+};
+__device__ __forceinline__ bool sel_less(const SelE<int32_t> &a, const SelE<int32_t> &b)
 {
+    return a.w < b.w;
+}
+__device__ __forceinline__ bool sel_less(const SelE<int64_t> &a, const SelE<int64_t> &b)
+{
+    if (!a.vp || !b.vp)
+        return !b.vp && (a.vp || a.r < b.r);
+    if (a.key != b.key)
+        return a.key < b.key;
+    const int32_t va = *a.vp, vb = *b.vp;
+    if (va != vb)
+        return va < vb;
+    return a.r < b.r;
+}
+template <typename T> struct SelWin {
+    const int32_t *k, *v;  // the window's first element
+    int64_t W;
+    __device__ __forceinline__ SelE<T> sentinel(int r) const
     {
-        const int64_t flo = kx > X.nq ? kx - X.nq : 0, fhi = kx < X.np ? kx : X.np;
-        lx = lx < flo ? flo : (lx > fhi ? fhi : lx);
-        hx = hx > fhi ? fhi : (hx < lx ? lx : hx);
+        if constexpr (sizeof(T) == 8)
+            return SelE<T>{0, r, nullptr};
+        else
+            return SelE<T>{((int64_t)1 << 40) | r};
     }
+    __device__ __forceinline__ SelE<T> at(int r, int64_t j) const
     {
-        const int64_t flo = ky > Y.nq ? ky - Y.nq : 0, fhi = ky < Y.np ? ky : Y.np;
-        ly = ly < flo ? flo : (ly > fhi ? fhi : ly);
-        hy = hy > fhi ? fhi : (hy < ly ? ly : hy);
-    }
-    while (lx < hx || ly < hy) {
-        const bool sx = lx < hx, sy = ly < hy;
-        const int64_t mx = lx + ((hx - lx) >> 1), my = ly + ((hy - ly) >> 1);
-        typename VRun<T>::E px{}, qx{}, py{}, qy{};
-        if (sx) {
-            px = X.P(mx);
-            qx = X.Q(kx - 1 - mx);
-        }
-        if (sy) {
-            py = Y.P(my);
-            qy = Y.Q(ky - 1 - my);
-        }
-        probes += (sx ? 1u : 0u) + (sy ? 1u : 0u);
-        if (sx) {
-            if (qx < px)
-                hx = mx;
-            else
-                lx = mx + 1;
-        }
-        if (sy) {
-            if (qy < py)
-                hy = my;
-            else
-                ly = my + 1;
-        }
-    }
-    rx = lx;
-    ry = ly;
-}
-
-// Co-ranks (x, a, c) of diagonal d (a multiple of tm) of X (+) Y.
-//
-// With a prediction (learned or linear mode), stage 1 first tests the two
-// grid points around the predicted splitter together and only bisects the
-// side that remains when they do not bracket it.
-//
-// x is the first m in [lo0, hi0) with Y[d-1-m] < X[m] (hi0 if none).
-// Stage 1 searches the sample grid: the two-way co-ranks a(k*tm) of X and
-// c(k*tm) of Y, which the two-way co-rank kernel computes for every tile of
-// a pass with the same run length (grid[gx + k], grid[gy + k]).  At a grid
-// point m = k*tm the test needs only element loads, since d - m is a grid
-// point of Y too.  That confines x to one interval of tm diagonals.
-// Stage 2 is a bisection inside it; every probe needs a(mid) and
-// c(d-1-mid), each confined to the interval that the current bracket's ends
-// allow (co-ranks are monotone and grow by at most one per diagonal), so
-// the inner searches shrink with the outer one.  Stage 2 invariants: x in
-// [lo, hi]; aL = a(lo), aH = a(hi); cL = c(d - hi), cH = c(d - lo).
-// (A cooperative variant with 16 lanes per tile and 16-way splits cuts the
-// dependent depth about threefold but issues several times the scattered
-// loads, and measured slower.)
-// The key of element 0 and of the last element of a virtual run (min of the
-// first keys, max of the last keys of its two runs).
-template <typename T>
-__device__ __forceinline__ void vrun_ends(const VRun<T> &V, int32_t &first, int32_t &last)
-{
-    const int32_t *pk = V.pk, *qk = V.qk;
-    if (V.np == 0) {
-        first = qk[0];
-        last = qk[V.nq - 1];
-    } else if (V.nq == 0) {
-        first = pk[0];
-        last = pk[V.np - 1];
-    } else {
-        first = min(pk[0], qk[0]);
-        last = max(pk[V.np - 1], qk[V.nq - 1]);
-    }
-}
-
-// Predicted split of diagonal d between X and Y (c.mode != 0): the
-// learned or proportional co-rank prediction of the two-way pass, applied
-// to the virtual runs X and Y through their end keys (for the model: where
-// its CDF puts them), i.e. the splitter of the four runs at rank d.
-template <typename T>
-__device__ int64_t predict_split(const Group<T> &G, int64_t d, const CorankCtl &c)
-{
-    const int64_t nx = G.X.len(), ny = G.Y.len();
-    if (nx == 0 || ny == 0)
-        return d < nx ? d : nx;
-    int32_t x0, x1, y0, y1;
-    vrun_ends<T>(G.X, x0, x1);
-    vrun_ends<T>(G.Y, y0, y1);
-    auto XK = [=](int64_t i) { return i == 0 ? x0 : x1; };
-    auto YK = [=](int64_t i) { return i == 0 ? y0 : y1; };
-    return predict_corank(c, XK, YK, nx, ny, d, nullptr);
-}
-
-template <typename T>
-__device__ Quad quad_corank(const Group<T> &G, int64_t d, int64_t tm, const int64_t *grid,
-                            int64_t gx, int64_t gy, unsigned &probes,
-                            const CorankCtl *pred = nullptr)
-{
-    const VRun<T> &X = G.X, &Y = G.Y;
-    const int64_t nx = X.len(), ny = Y.len();
-    const int64_t lo0 = d > ny ? d - ny : 0, hi0 = d < nx ? d : nx;
-    const int64_t mask = tm - 1;
-    // a(m) / c(k) at a run end or a grid point; elsewhere (the ragged last
-    // group only) by a full search
-    auto ga = [&](int64_t m) {
-        return m == nx ? X.np : ((m & mask) == 0 ? grid[gx + m / tm] : X.rank(m, 0, X.np, probes));
-    };
-    auto gc = [&](int64_t k) {
-        return k == ny ? Y.np : ((k & mask) == 0 ? grid[gy + k / tm] : Y.rank(k, 0, Y.np, probes));
-    };
-
-    // stage 1: first grid point k*tm in [lo0, hi0) whose test holds
-    int64_t klo = (lo0 + mask) / tm, khi = (hi0 + mask) / tm;
-    auto test = [&](int64_t k) {  // Y[d-1-m] < X[m] at m = k*tm, k in [klo, khi)
-        const int64_t m = k * tm;
-        const int64_t am = grid[gx + k];  // m < hi0 <= nx
-        const int64_t ym = d - m;         // in [1, ny], a multiple of tm
-        const int64_t cm = ym == ny ? Y.np : grid[gy + ym / tm];
-        bool f;
-        ++probes;
-        return Y.last(ym, cm) < X.at(m, am, f);
-    };
-    if (pred && khi - klo > 2) {
-        // predicted splitter: test the grid points around it together; the
-        // answer is exact when they bracket it, else the bisection goes on
-        // in the remaining side
-        int64_t k = predict_split<T>(G, d, *pred) / tm;
-        k = k < klo ? klo : (k > khi - 2 ? khi - 2 : k);
-        const bool t0 = test(k), t1 = test(k + 1);
-        if (t0)
-            khi = k;
-        else if (t1)
-            klo = khi = k + 1;
+        if (j >= W)
+            return sentinel(r);
+        if constexpr (sizeof(T) == 8)
+            return SelE<T>{k[j], r, v + j};
         else
-            klo = k + 2;
+            return SelE<T>{((int64_t)k[j] << 2) | r};
     }
-    while (klo < khi) {
-        const int64_t k = (klo + khi) >> 1;
-        if (test(k))
-            khi = k;
-        else
-            klo = k + 1;
-    }
-    int64_t lo = (klo - 1) * tm > lo0 ? (klo - 1) * tm : lo0;
-    int64_t hi = klo * tm < hi0 ? klo * tm : hi0;
-    int64_t aL = ga(lo), aH = ga(hi), cL = gc(d - hi), cH = gc(d - lo);
+};
 
-    // stage 2
-    while (lo < hi) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        const int64_t y = d - 1 - mid;
-        int64_t am, ym;
-        rank2<T>(X, mid, aL > mid - hi + aH ? aL : mid - hi + aH, aH < mid - lo + aL ? aH : mid - lo + aL,
-                 am, Y, y, cL > y - (d - lo) + cH ? cL : y - (d - lo) + cH,
-                 cH < y - (d - hi) + cL ? cH : y - (d - hi) + cL, ym, probes);
-        bool fx, fy;
-        const auto xv = X.at(mid, am, fx);
-        const auto yv = Y.at(y, ym, fy);
-        if (yv < xv) {  // X[mid] comes after Y[d-1-mid]: x <= mid
-            hi = mid;
-            aH = am;
-            cL = ym + (fy ? 1 : 0);
-        } else {
-            lo = mid + 1;
-            aL = am + (fx ? 1 : 0);
-            cH = ym;
+// Counts (w_0..w_3) of the D smallest elements of four windows (D at most
+// the sum of their widths).  Stride halving: at stride s the samples of a
+// window are its elements at positions j*s - 1, and the selection at that
+// stride is the floor(D / s) smallest samples (w_r of them in window r, the
+// first w_r of its samples); at s = 1 that is the answer.  From stride 2s
+// to s, every selected sample brings the sample before it, and outside
+// those only the sample after each window's last selected one (its
+// candidate c_r) can lie below the largest selected sample y, so the
+// samples up to y are the 2 * old count plus the candidates below y; the
+// new count floor(D / s) is within one of twice the old one, so at most
+// three of them go again (the largest first) or the smallest candidate
+// joins.  Each level reads the four candidates and the sample before each
+// window's top together (the top's replacement after a removal), so a
+// level costs one round of independent loads; a second removal from one
+// window (rare) reads one more.  About log2(width) + 1 rounds in all,
+// against log2(width)^2 / 2 for the nested bisection.
+// Strides below which the sample before a window's top is read ahead with
+// the candidates: there it shares a cache line with the top.  At larger
+// strides reading it ahead doubles the lines a level fetches, and the kernel
+// is bound by those line fetches; a removal then reads it when needed.
+constexpr int64_t kSelReadAhead = 32;
+template <typename T>
+__device__ __forceinline__ void select4(const SelWin<T> (&S)[4], int64_t D, int64_t (&w)[4],
+                                        unsigned &probes)
+{
+    using E = SelE<T>;
+    int64_t mw = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        w[r] = 0;
+        mw = S[r].W > mw ? S[r].W : mw;
+    }
+    const int lgL = mw <= 1 ? 0 : 64 - __builtin_clzll((uint64_t)(mw - 1));
+    E top[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        top[r] = S[r].sentinel(r);
+    for (int lg = lgL; lg >= 0; --lg) {
+        const int64_t s = (int64_t)1 << lg;
+        const int64_t tn = D >> lg;
+        int64_t b2[4];
+        E c[4], p[4], ot[4];
+        bool any = false, ld = false;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            b2[r] = 2 * w[r];
+            w[r] = b2[r];
+            ot[r] = top[r];
+            const int64_t jc = (b2[r] + 1) * s - 1, jp = (b2[r] - 1) * s - 1;
+            c[r] = S[r].at(r, jc);
+            p[r] = (b2[r] > 0 && s < kSelReadAhead) ? S[r].at(r, jp) : S[r].sentinel(r);
+            ld |= jc < S[r].W || (b2[r] > 0 && s < kSelReadAhead && jp < S[r].W);
+            any |= b2[r] > 0;
+        }
+        probes += ld ? 1u : 0u;
+        int64_t cnt = 0;
+        if (any) {
+            E y = S[0].sentinel(0);
+            bool have = false;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (w[r] > 0 && (!have || sel_less(y, top[r]))) {
+                    y = top[r];
+                    have = true;
+                }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (sel_less(c[r], y)) {
+                    w[r] += 1;
+                    top[r] = c[r];
+                }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            cnt += w[r];
+        for (; cnt > tn; --cnt) {  // at most three times
+            int rm = -1;
+            E m = S[0].sentinel(0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (w[r] > 0 && (rm < 0 || sel_less(m, top[r]))) {
+                    rm = r;
+                    m = top[r];
+                }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r == rm) {
+                    w[r] -= 1;
+                    const int64_t q = w[r] - b2[r];
+                    if (w[r] > 0) {
+                        if (q == 0)
+                            top[r] = ot[r];
+                        else if (q == -1 && s < kSelReadAhead)
+                            top[r] = p[r];
+                        else {
+                            ++probes;
+                            top[r] = S[r].at(r, w[r] * s - 1);
+                        }
+                    }
+                }
+        }
+        for (; cnt < tn; ++cnt) {  // one candidate, or up to four at the first level
+            int ra = -1;
+            E m = S[0].sentinel(0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                // past the candidate only the first level gets here, where
+                // the next sample lies past the window: a sentinel
+                const E nx = w[r] == b2[r] ? c[r] : S[r].sentinel(r);
+                if (ra < 0 || sel_less(nx, m)) {
+                    ra = r;
+                    m = nx;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r == ra) {
+                    w[r] += 1;
+                    top[r] = m;
+                }
         }
     }
-    Quad q;
-    q.x = lo;
-    q.a = aL;
-    q.c = cH;
-    return q;
+}
+
+// Co-ranks (x, a, c) of diagonal d of X (+) Y: the shares of A, B, C and D
+// among the d smallest elements of the group, selected in the four whole
+// runs (x = a + b: X's share).
+template <typename T>
+__device__ __forceinline__ Quad quad_corank(const Group<T> &G, int64_t d, unsigned &probes)
+{
+    SelWin<T> S[4];
+    S[0] = SelWin<T>{G.X.pk, G.X.pv, G.X.np};
+    S[1] = SelWin<T>{G.X.qk, G.X.qv, G.X.nq};
+    S[2] = SelWin<T>{G.Y.pk, G.Y.pv, G.Y.np};
+    S[3] = SelWin<T>{G.Y.qk, G.Y.qv, G.Y.nq};
+    int64_t w[4];
+    select4<T>(S, d, w, probes);
+    return Quad{w[0] + w[1], w[0], w[2]};
 }
 
 struct Tile4 {
@@ -445,10 +369,8 @@ __global__ __launch_bounds__(64) void quad_corank_kernel(const int32_t *__restri
                                                           const int32_t *__restrict__ vin,
                                                           int64_t n, int64_t run, int64_t tm,
                                                           int64_t ntiles, int lg4run,
-                                                          const int64_t *__restrict__ grid,
                                                           TileRec *__restrict__ out,
-                                                          unsigned long long *stats,
-                                                          CorankCtl pc)
+                                                          unsigned long long *stats)
 {
     const int l = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 63 + l;
@@ -458,8 +380,7 @@ __global__ __launch_bounds__(64) void quad_corank_kernel(const int32_t *__restri
         const int64_t o0 = g * tm;
         G = group_of<T>(kin, vin, n, run, o0 >> lg4run);
         unsigned probes = 0;
-        q = quad_corank<T>(G, o0 - G.gb, tm, grid, G.gb / tm, (G.gb + 2 * run) / tm, probes,
-                           pc.mode != 0 ? &pc : nullptr);
+        q = quad_corank<T>(G, o0 - G.gb, probes);
         if (stats && l < 63) {
             atomicAdd(stats + 0, 1ull);
             atomicAdd(stats + 1, (unsigned long long)probes);
@@ -483,18 +404,15 @@ __global__ __launch_bounds__(64) void quad_corank_kernel(const int32_t *__restri
 }
 
 // The same for the four-way tiles of a segmented pass: tile q of the list is
-// tile j of its segment, whose tiles sit at list positions q - j .. (so the
-// segment's grid entries do too).  Each record's chunk bases are absolute;
+// tile j of its segment.  Each record's chunk bases are absolute;
 // obase[q] is the tile's first output index, bit 62 marking a segment whose
 // data sits in scratch.
 template <typename T>
 __global__ __launch_bounds__(64) void seg_quad_corank_kernel(SegMap map, int64_t run, int64_t tm,
                                                               int lg4run,
-                                                              const int64_t *__restrict__ grid,
                                                               TileRec *__restrict__ out,
                                                               int64_t *__restrict__ obase,
-                                                              unsigned long long *stats,
-                                                              CorankCtl pc)
+                                                              unsigned long long *stats)
 {
     const int l = threadIdx.x;
     const int64_t q = (int64_t)blockIdx.x * 63 + l;
@@ -514,10 +432,8 @@ __global__ __launch_bounds__(64) void seg_quad_corank_kernel(SegMap map, int64_t
         const int32_t *iv = odd ? map.scrv : map.outv;
         o0 = (int64_t)j * tm;
         G = group_of<T>(ik + base, iv ? iv + base : nullptr, len, run, o0 >> lg4run);
-        const int64_t q0 = q - j;
         unsigned probes = 0;
-        qd = quad_corank<T>(G, o0 - G.gb, tm, grid, q0 + G.gb / tm, q0 + (G.gb + 2 * run) / tm,
-                            probes, pc.mode != 0 ? &pc : nullptr);
+        qd = quad_corank<T>(G, o0 - G.gb, probes);
         if (stats && l < 63) {
             atomicAdd(stats + 0, 1ull);
             atomicAdd(stats + 1, (unsigned long long)probes);
@@ -867,28 +783,16 @@ size_t merge4_record_bytes() { return sizeof(TileRec); }
 
 template <typename T>
 static hipError_t launch_quad_corank(const int32_t *kin, const int32_t *vin, int64_t n,
-                                     int64_t run, int64_t tm, const int64_t *grid, void *rec,
-                                     const CorankOpts &o, hipStream_t s)
+                                     int64_t run, int64_t tm, void *rec,
+                                     unsigned long long *stats, hipStream_t s)
 {
     const int64_t ntiles = (n + tm - 1) / tm;
-    // one thread per tile, one wave per workgroup: the chains of dependent
-    // probes spread over all CUs (256-thread workgroups left half of them
-    // idle at 2^28 keys and measured 3 % slower per sort).  In the learned
-    // and linear modes each tile first tests the grid interval its predicted
-    // splitter falls in (the kernel counts the stats itself).
-    CorankCtl pc;
-    pc.mode = o.mode;
-    pc.radius_log2 = o.radius_log2;
-    pc.cdf = o.cdf;
-    pc.stats = nullptr;
-    pc.pair_cdf = nullptr;
-    pc.pair_first = 0;
-    pc.table = o.table;
-    if (pc.mode == 1 && !pc.table)  // no table: proportional split
-        pc.mode = 2;
+    // one thread per tile, one wave per workgroup: the tiles' selections
+    // spread over all CUs (256-thread workgroups left half of them idle at
+    // 2^28 keys and measured 3 % slower per sort)
     hipLaunchKernelGGL(quad_corank_kernel<T>, dim3((unsigned)((ntiles + 62) / 63)), dim3(64), 0,
-                       s, kin, vin, n, run, tm, ntiles, ilog2_pow2(4 * run), grid, (TileRec *)rec,
-                       o.stats, pc);
+                       s, kin, vin, n, run, tm, ntiles, ilog2_pow2(4 * run), (TileRec *)rec,
+                       stats);
     return hipGetLastError();
 }
 
@@ -929,19 +833,14 @@ static hipError_t launch_m4(const int32_t *kin, const int32_t *vin, int32_t *kou
 }
 
 hipError_t launch_merge4_corank(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
-                                int64_t n, int64_t run, int64_t *grid, void *rec,
-                                const CorankOpts &o, hipStream_t s)
+                                int64_t n, int64_t run, void *rec, const CorankOpts &o,
+                                hipStream_t s)
 {
-    // the sample grid: two-way co-ranks of every tile-aligned diagonal of the
-    // pairs (A, B) and (C, D) of each group (2*run is a multiple of tm)
     // runs are powers of two (the kernels find a tile's group by a shift)
     if (!merge4_supported(tm, pairs) || run <= 0 || (run & (run - 1)) != 0 || (2 * run) % tm != 0)
         return hipErrorInvalidValue;
-    hipError_t e = launch_pass_corank(pairs, kin, vin, n, run, tm, grid, o, s);
-    if (e != hipSuccess)
-        return e;
-    return pairs ? launch_quad_corank<int64_t>(kin, vin, n, run, tm, grid, rec, o, s)
-                 : launch_quad_corank<int32_t>(kin, nullptr, n, run, tm, grid, rec, o, s);
+    return pairs ? launch_quad_corank<int64_t>(kin, vin, n, run, tm, rec, o.stats, s)
+                 : launch_quad_corank<int32_t>(kin, nullptr, n, run, tm, rec, o.stats, s);
 }
 
 hipError_t launch_merge4_pass(int tm, bool pairs, const int32_t *kin, const int32_t *vin,
@@ -990,27 +889,21 @@ static hipError_t launch_m4_seg(const SegMap &map, int64_t n_total, int64_t run,
     return hipGetLastError();
 }
 
-hipError_t launch_seg_merge4(int tm, bool pairs, const SegMap &map, int64_t run,
-                             const int64_t *grid, void *rec, int64_t *obase, int64_t max_tiles,
-                             int64_t n_total, const CorankCtl &pc_in, int occupancy, hipStream_t s)
+hipError_t launch_seg_merge4(int tm, bool pairs, const SegMap &map, int64_t run, void *rec,
+                             int64_t *obase, int64_t max_tiles, int64_t n_total,
+                             unsigned long long *stats, int occupancy, hipStream_t s)
 {
     if (!merge4_supported(tm, pairs) || run <= 0 || (run & (run - 1)) != 0 || (2 * run) % tm != 0 ||
         max_tiles <= 0)
         return hipErrorInvalidValue;
-    CorankCtl pc = pc_in;
-    pc.stats = nullptr;  // the kernel counts its probes itself
-    pc.pair_cdf = nullptr;
-    pc.pair_first = 0;
-    if (pc.mode == 1 && !pc.table)  // no table: proportional split
-        pc.mode = 2;
     const unsigned qb = (unsigned)((max_tiles + 62) / 63);
     const int lg = ilog2_pow2(4 * run);
     if (pairs)
         hipLaunchKernelGGL(seg_quad_corank_kernel<int64_t>, dim3(qb), dim3(64), 0, s, map, run,
-                           (int64_t)tm, lg, grid, (TileRec *)rec, obase, pc_in.stats, pc);
+                           (int64_t)tm, lg, (TileRec *)rec, obase, stats);
     else
         hipLaunchKernelGGL(seg_quad_corank_kernel<int32_t>, dim3(qb), dim3(64), 0, s, map, run,
-                           (int64_t)tm, lg, grid, (TileRec *)rec, obase, pc_in.stats, pc);
+                           (int64_t)tm, lg, (TileRec *)rec, obase, stats);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;

@@ -800,23 +800,13 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
             continue;
         }
         // four-way launch p: runs of TILE * 4^p; first the four-way tiles
-        // (the grid of two-way co-ranks, then the four-way co-ranks and the
-        // merge), then the two-way tiles of the segments with one level left
+        // (their co-rank records, then the merge), then the two-way tiles of
+        // the segments with one level left
         const int64_t run = tile << (2 * p);
         SegMap m4 = map;
         m4.pass_tiles = (const int64_t *)(ctrl + C_PASSF);
-        const unsigned cb = (unsigned)((L.max_tiles + 63) / 64);
-        if (pairs)
-            hipLaunchKernelGGL(seg_corank_kernel<int64_t>, dim3(cb), dim3(64), 0, s, m4, run,
-                               (int64_t)a.TM, cr, c);
-        else
-            hipLaunchKernelGGL(seg_corank_kernel<int32_t>, dim3(cb), dim3(64), 0, s, m4, run,
-                               (int64_t)a.TM, cr, c);
-        e = hipGetLastError();
-        if (e != hipSuccess)
-            return e;
-        e = launch_seg_merge4(a.TM, pairs, m4, run, cr, ws + L.rec, (int64_t *)(ws + L.obase),
-                              L.max_tiles, a.n_total, c, a.occupancy, s);
+        e = launch_seg_merge4(a.TM, pairs, m4, run, ws + L.rec, (int64_t *)(ws + L.obase),
+                              L.max_tiles, a.n_total, c.stats, a.occupancy, s);
         if (e != hipSuccess)
             return e;
         SegMap m2 = map;

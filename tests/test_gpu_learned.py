@@ -163,27 +163,31 @@ def test_learned_sort_is_exact(dist):
 def test_full_size_2pow30_learned():
     # the learned co-rank's own configuration: 2^30 mixture keys, the CDF
     # model trained on the GPU from a 1 % sample, learned co-ranks with the
-    # bounded search (radius 2^13) in the tuned launch shape, element by
-    # element against the oracle (run in parts on the host); the linear and
-    # binary modes must give the identical array
+    # bounded search (radius 2^13) in the best two-way launch shape (every
+    # co-rank predicted), element by element against the oracle (run in
+    # parts on the host); the linear and binary modes, and the tuned
+    # four-way shape in every mode, must give the identical array
     import oracle_parts
     from paper_2409_03970_amd import tune
     n = 1 << 30
     print("full size 2^30 learned", flush=True)
     x = inputs.keys(n, "mixture", seed=0, device=DEV)
     params = hv.fit_cdf_model(x, frac=0.01, steps=400, batch=65536, lr=3e-3, seed=2)
-    opts = dict(tune.tuned_options("sort", n) or {})
+    two = dict(tune.tuned_options("sort", n, two_way=True) or {}, merge_ways=2)
     st = torch.zeros(hv.STATS_WORDS, dtype=torch.int64, device=DEV)
-    y = hv.sort(x, opts=dict(opts, corank_mode=hv.CORANK_LEARNED, cdf_params=params,
+    y = hv.sort(x, opts=dict(two, corank_mode=hv.CORANK_LEARNED, cdf_params=params,
                              radius_log2=13, stats=st))
     torch.cuda.synchronize()
     s = hv.corank_stats(st.cpu())
     assert s["coranks"] > 0 and s.get("predicted", 0) > 0
     want = oracle_parts.sort_in_parts(x.cpu().numpy(), parts=16, threads=16)
     assert np.array_equal(y.cpu().numpy(), want)
-    for mode in (hv.CORANK_LINEAR, hv.CORANK_BINARY):
+    del want
+    four = dict(tune.tuned_options("sort", n) or {})
+    for opts, mode in ((two, hv.CORANK_LINEAR), (two, hv.CORANK_BINARY),
+                       (four, hv.CORANK_LEARNED), (four, hv.CORANK_BINARY)):
         y2 = hv.sort(x, opts=dict(opts, corank_mode=mode, cdf_params=params, radius_log2=13))
-        assert torch.equal(y2, y), mode
+        assert torch.equal(y2, y), (opts.get("merge_ways"), mode)
         del y2
 
 
@@ -210,13 +214,14 @@ def test_learned_prediction_exact_on_disjoint_runs():
     assert sum(learned[72:136]) == learned[5] == learned[72]
 
 
-def _check_histograms(w, mode):
+def _check_histograms(w, mode, predicts=True):
+    # predicts: the sort has two-way co-ranks (four-way ones use no prediction)
     n = w[0]
     ph, eh = w[8:72], w[72:136]
     assert sum(ph) == n                                         # every co-rank in one bin
     if ph[63] == 0:
         assert sum(p * h for p, h in enumerate(ph)) == w[1]      # exact probe total
-    if mode == hv.CORANK_BINARY:
+    if mode == hv.CORANK_BINARY or (not predicts and w[5] == 0):
         assert w[5] == 0 and sum(eh) == 0 and w[2] == w[3] == w[4] == 0
         return
     assert 0 < w[5] <= n and sum(eh) == w[5] and w[2] <= w[5]
@@ -241,7 +246,7 @@ def test_corank_histograms_are_consistent(dist, ways):
         assert np.array_equal(y.cpu().numpy(), want)
         w = st.cpu().tolist()
         assert w[0] > 0
-        _check_histograms(w, mode)
+        _check_histograms(w, mode, predicts=ways == 2)
         s = hv.corank_stats(w)
         assert s["probes_p99"] is not None and s["probes_p99"] * 1.0 >= 0
 
