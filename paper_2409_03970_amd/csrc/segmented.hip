@@ -132,15 +132,19 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned lo
         if (size > 0) {
             const int64_t tile = (int64_t)1 << P.tile_log2;
             if (size <= tile) {
-                atomicAdd(&cnt[bucket_of(P, size)], 1ull);
+                // more than half a tile: a (padded) piece of the full-piece list
+                if (2 * size > tile)
+                    atomicAdd(&full, 1ull);
+                else
+                    atomicAdd(&cnt[bucket_of(P, size)], 1ull);
             } else {
-                // full pieces go to the full-piece list, a ragged rest to the
-                // bucket of its own size
+                // full pieces go to the full-piece list, a ragged rest too if
+                // it is more than half a tile, else to the bucket of its size
                 const int64_t np = (size + tile - 1) / tile;
                 const int ps = ceil_log2(np);
                 const int64_t nfull = size / tile, rest = size - nfull * tile;
-                atomicAdd(&full, (unsigned long long)nfull);
-                if (rest)
+                atomicAdd(&full, (unsigned long long)(nfull + (2 * rest > tile ? 1 : 0)));
+                if (rest && 2 * rest <= tile)
                     atomicAdd(&cnt[bucket_of(P, rest)], 1ull);
                 atomicAdd(&lcnt[ps], 1ull);
                 atomicAdd(&tcnt[ps], (unsigned long long)((size + P.tm - 1) / P.tm));
@@ -251,25 +255,26 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
     __syncthreads();
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tile = (int64_t)1 << P.tile_log2;
-    int64_t size = 0, nfull = 0, nt = 0, o = 0;
+    int64_t size = 0, nfull = 0, nt = 0, o = 0, rest = 0;
     int b = -1, ps = 0;
+    bool ragged = false;  // the segment, or its rest, is a padded full-list piece
     unsigned long long mine = 0, tmine = 0, fmine = 0;
     if (s < P.nseg) {
         o = P.off[s];
         const int64_t e = P.off[s + 1];
         size = (o >= 0 && e <= P.n_total && e >= o) ? e - o : 0;
         if (size > 0) {
-            if (size <= tile) {
-                b = bucket_of(P, size);
-            } else {
-                nfull = size / tile;
-                const int64_t rest = size - nfull * tile;
-                b = rest ? bucket_of(P, rest) : -1;
+            nfull = size > tile ? size / tile : 0;
+            rest = size - nfull * tile;
+            ragged = 2 * rest > tile;
+            b = (rest && !ragged) ? bucket_of(P, rest) : -1;
+            if (size > tile) {
                 ps = ceil_log2((size + tile - 1) / tile);
                 nt = (size + P.tm - 1) / P.tm;
                 tmine = atomicAdd(&tcnt[ps], (unsigned long long)nt);
-                fmine = atomicAdd(&fcnt, (unsigned long long)nfull);
             }
+            if (nfull || ragged)
+                fmine = atomicAdd(&fcnt, (unsigned long long)(nfull + (ragged ? 1 : 0)));
             if (b >= 0)
                 mine = atomicAdd(&cnt[b], 1ull);
         }
@@ -299,10 +304,11 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
         pc.dst = dst;
         pieces[bbase[b] + mine] = pc;
     }
-    for (int64_t i = 0; i < nfull && fbase + fmine + i < (unsigned long long)P.max_full; ++i) {
+    const int64_t nlist = nfull + (ragged ? 1 : 0);
+    for (int64_t i = 0; i < nlist && fbase + fmine + i < (unsigned long long)P.max_full; ++i) {
         Piece pc;
         pc.off = o + i * tile;
-        pc.len = (int32_t)tile;
+        pc.len = (int32_t)(i < nfull ? tile : rest);
         pc.dst = dst;
         fulls[fbase + fmine + i] = pc;
     }
@@ -318,7 +324,11 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
 // presorted-tile test, column sort, in-register merge levels, LDS merge
 // levels), one workgroup per entry of the full-piece list.  R and NT are
 // chosen for the tile size (R = 32 where it fits), independent of the packed
-// kernel's, which must also serve tiny segments.
+// kernel's, which must also serve tiny segments.  The list also holds the
+// segments and ragged rests of more than half a tile: such a piece is padded
+// with the maximum of the order and sorted whole, and its first len outputs
+// are stored (a workgroup-uniform branch; the packed kernel at its smaller R
+// sorts a tile about half as fast).
 template <int R, int NT, typename T>
 __global__ __launch_bounds__(NT) void seg_full_kernel(int wave_levels, int lds_levels,
                                                       const unsigned long long *ctrl,
@@ -346,6 +356,24 @@ __global__ __launch_bounds__(NT) void seg_full_kernel(int wave_levels, int lds_l
         const int32_t *pv = sizeof(T) == 8 ? iv + pc.off : nullptr;
         int32_t *dk = (pc.dst ? sk : ok) + pc.off;
         int32_t *dv = sizeof(T) == 8 ? (pc.dst ? sv : ov) + pc.off : nullptr;
+        if (pc.len != TILE) {  // workgroup-uniform: a padded piece
+            const int len = pc.len;
+            const int rel = wave * (64 * R) + lane;
+            T v[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int p = rel + 64 * j;
+                v[j] = p < len ? load_elem<T>(pk, pv, p) : Traits<T>::kMax;
+            }
+            sort_tile_core<R, NT>(S, v, t, wave_levels, lds_levels);
+            const T *zt = S + LdsSkew<T>::pos(t);
+            constexpr int ZS = LdsSkew<T>::size(NT);
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                if (t + NT * j < len)
+                    store_elem<T>(dk, dv, t + NT * j, zt[ZS * j]);
+            return;
+        }
         // buffer loads and stores: a lane offset plus a wave-uniform one
         const TileIO<T> in(pk, pv, TILE), out(dk, dv, TILE);
         const int wb = __builtin_amdgcn_readfirstlane(wave) * (64 * R);
@@ -548,7 +576,8 @@ SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool 
     SegLayout L{};
     const int64_t tile = (int64_t)R * NT;
     const int64_t max_pieces = nseg + 2 * (n_total / tile) + 2;
-    const int64_t max_full = n_total / tile + 1;
+    // full pieces and padded pieces of more than half a tile, all disjoint
+    const int64_t max_full = 2 * (n_total / tile) + 2;
     const int64_t max_tiles = n_total / TM + n_total / tile + 2;
     int64_t o = 0;
     L.ctrl = o;
