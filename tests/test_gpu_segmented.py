@@ -491,3 +491,21 @@ def test_four_way_learned_corank_segments():
     assert torch.equal(y, hv.segmented_sort(k, offs, opts={"merge_ways": 4, "merge_tile": 4096}))
     s = hv.corank_stats(st.cpu())
     assert s["coranks"] > 0 and s.get("predicted", 0) > 0
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+@pytest.mark.parametrize("ways", [2, 4])
+@pytest.mark.parametrize("dist", ["uniform", "sorted", "distinct16"])
+def test_pieces_around_half_a_tile(pairs, ways, dist):
+    # segments, and ragged rests of longer segments, at the half-tile line:
+    # up to half a tile they go to the packed kernel, above it (padded with
+    # the maximum) to the full-piece kernel; a tile of 4096 keys
+    T, H = 4096, 2048
+    sizes = []
+    for r in (H - 1, H, H + 1, H + 2, T - 1, T):
+        sizes += [r, T + r, 3 * T + r, 8 * T + r]
+    sizes += [T + 1, 2 * T, 5 * T + H + 1, 0, 1, H + 1]
+    _say("pieces around half a tile", pairs, ways, dist)
+    _run(sizes, dist=dist, seed=17, pairs=pairs,
+         opts={"keys_per_lane": 8, "block_threads": 512, "merge_tile": 4096,
+               "merge_ways": ways})
