@@ -107,7 +107,7 @@ inline int ceil_log2_host(int64_t x)
 struct SegLayout {
     int64_t ctrl, pieces, fulls, tiles, cr, rec, obase, passes, table, scr_k, scr_v, total,
         max_tiles,
-        max_pieces, max_full;
+        max_pieces, max_full, max_half;
 };
 SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool pairs,
                      int ways = 2);

@@ -52,8 +52,10 @@ enum : int {
     C_OVER,                         // segments with P_s above the enqueued passes
     C_SKIP,                         // segments skipped: offsets outside [0, n_total] or decreasing
     C_BAD,                          // 1: offsets inconsistent with n_total, nothing sorted
-    C_FULL,                         // full pieces (TILE keys of a longer segment)
+    C_FULL,                         // full-list pieces (a tile, or padded: more than half a tile)
     C_FCUR,                         // scatter cursor of the full-piece list
+    C_HALF,                         // half-list pieces (more than a quarter, at most half a tile)
+    C_HCUR,                         // scatter cursor of the half list
     C_LCNT = 80,                    // large segments with P_s == P
     C_TCNT = C_LCNT + kMaxP,        // merge tiles of those segments
     C_TCUR = C_TCNT + kMaxP,        // tile-list cursors per P
@@ -80,7 +82,7 @@ __device__ __forceinline__ int ceil_log2(int64_t x)
 struct SegParams {
     const int64_t *off;
     int64_t nseg, n_total;
-    int64_t max_pieces, max_tiles, max_full;  // list capacities in the workspace
+    int64_t max_pieces, max_tiles, max_full, max_half;  // list capacities in the workspace
     int tile_log2, r_log2, nb;  // nb = buckets = tile_log2 - r_log2 + 1
     int passes;                 // merge launches enqueued by the host
     int ways;                   // 2 or 4 runs merged per launch
@@ -91,6 +93,15 @@ struct SegParams {
 __device__ __forceinline__ int launches_of(const SegParams &P, int L)
 {
     return P.ways == 4 ? (L + 1) >> 1 : L;
+}
+
+// Where a piece (a segment of at most a tile, or a longer segment's ragged
+// rest) of len keys is sorted: 2 the full-piece list (more than half a tile,
+// padded), 1 the half list (more than a quarter: two per full-kernel tile,
+// each padded to half a tile), 0 the packed kernel's bucket of its size.
+__device__ __forceinline__ int piece_class(int64_t len, int64_t tile)
+{
+    return 2 * len > tile ? 2 : (4 * len > tile ? 1 : 0);
 }
 
 __device__ __forceinline__ int bucket_of(const SegParams &P, int64_t size)
@@ -107,7 +118,8 @@ __global__ void seg_init_kernel(unsigned long long *ctrl)
 
 __global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned long long *ctrl)
 {
-    __shared__ unsigned long long cnt[kMaxBuckets], lcnt[kMaxP], tcnt[kMaxP], over, skip, full;
+    __shared__ unsigned long long cnt[kMaxBuckets], lcnt[kMaxP], tcnt[kMaxP], over, skip, full,
+        half;
     for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
         lcnt[i] = 0;
         tcnt[i] = 0;
@@ -118,6 +130,7 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned lo
         over = 0;
         skip = 0;
         full = 0;
+        half = 0;
     }
     __syncthreads();
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -131,21 +144,19 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned lo
             atomicAdd(&skip, 1ull);
         if (size > 0) {
             const int64_t tile = (int64_t)1 << P.tile_log2;
-            if (size <= tile) {
-                // more than half a tile: a (padded) piece of the full-piece list
-                if (2 * size > tile)
-                    atomicAdd(&full, 1ull);
-                else
-                    atomicAdd(&cnt[bucket_of(P, size)], 1ull);
-            } else {
-                // full pieces go to the full-piece list, a ragged rest too if
-                // it is more than half a tile, else to the bucket of its size
+            // full pieces go to the full-piece list, the segment itself (at
+            // most a tile) or a longer one's ragged rest where piece_class says
+            const int64_t nfull = size > tile ? size / tile : 0, rest = size - nfull * tile;
+            const int cls = piece_class(rest, tile);
+            if (nfull || cls == 2)
+                atomicAdd(&full, (unsigned long long)(nfull + (cls == 2 ? 1 : 0)));
+            if (cls == 1)
+                atomicAdd(&half, 1ull);
+            else if (cls == 0 && rest)
+                atomicAdd(&cnt[bucket_of(P, rest)], 1ull);
+            if (size > tile) {
                 const int64_t np = (size + tile - 1) / tile;
                 const int ps = ceil_log2(np);
-                const int64_t nfull = size / tile, rest = size - nfull * tile;
-                atomicAdd(&full, (unsigned long long)(nfull + (2 * rest > tile ? 1 : 0)));
-                if (rest && 2 * rest <= tile)
-                    atomicAdd(&cnt[bucket_of(P, rest)], 1ull);
                 atomicAdd(&lcnt[ps], 1ull);
                 atomicAdd(&tcnt[ps], (unsigned long long)((size + P.tm - 1) / P.tm));
                 if (launches_of(P, ps) > P.passes)
@@ -161,6 +172,8 @@ __global__ __launch_bounds__(256) void seg_count_kernel(SegParams P, unsigned lo
             atomicAdd(&ctrl[C_SKIP], skip);
         if (full)
             atomicAdd(&ctrl[C_FULL], full);
+        if (half)
+            atomicAdd(&ctrl[C_HALF], half);
     }
     for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
         if (lcnt[i])
@@ -192,7 +205,8 @@ __global__ __launch_bounds__(64) void seg_plan_kernel(SegParams P, unsigned long
             tiles_total += tcnt[p];
         bad = pieces > (unsigned long long)P.max_pieces ||
               tiles_total > (unsigned long long)P.max_tiles ||
-              ctrl[C_FULL] > (unsigned long long)P.max_full;
+              ctrl[C_FULL] > (unsigned long long)P.max_full ||
+              ctrl[C_HALF] > (unsigned long long)P.max_half;
     }
     __syncthreads();
     if (bad) {
@@ -241,24 +255,28 @@ __global__ __launch_bounds__(64) void seg_plan_kernel(SegParams P, unsigned long
 
 __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned long long *ctrl,
                                                           Piece *pieces, Piece *fulls,
-                                                          int2 *tiles, int32_t *passes)
+                                                          Piece *halves, int2 *tiles,
+                                                          int32_t *passes)
 {
     __shared__ unsigned long long cnt[kMaxBuckets], bbase[kMaxBuckets], tcnt[kMaxP], tbase[kMaxP];
-    __shared__ unsigned long long fcnt, fbase;
+    __shared__ unsigned long long fcnt, fbase, hcnt, hbase;
     for (int i = threadIdx.x; i < kMaxP; i += blockDim.x) {
         tcnt[i] = 0;
         if (i < kMaxBuckets)
             cnt[i] = 0;
     }
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         fcnt = 0;
+        hcnt = 0;
+    }
     __syncthreads();
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tile = (int64_t)1 << P.tile_log2;
     int64_t size = 0, nfull = 0, nt = 0, o = 0, rest = 0;
     int b = -1, ps = 0;
     bool ragged = false;  // the segment, or its rest, is a padded full-list piece
-    unsigned long long mine = 0, tmine = 0, fmine = 0;
+    bool halfp = false;   // ... or a half-list piece
+    unsigned long long mine = 0, tmine = 0, fmine = 0, hmine = 0;
     if (s < P.nseg) {
         o = P.off[s];
         const int64_t e = P.off[s + 1];
@@ -266,8 +284,10 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
         if (size > 0) {
             nfull = size > tile ? size / tile : 0;
             rest = size - nfull * tile;
-            ragged = 2 * rest > tile;
-            b = (rest && !ragged) ? bucket_of(P, rest) : -1;
+            const int cls = piece_class(rest, tile);
+            ragged = cls == 2;
+            halfp = cls == 1;
+            b = (rest && cls == 0) ? bucket_of(P, rest) : -1;
             if (size > tile) {
                 ps = ceil_log2((size + tile - 1) / tile);
                 nt = (size + P.tm - 1) / P.tm;
@@ -275,6 +295,8 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
             }
             if (nfull || ragged)
                 fmine = atomicAdd(&fcnt, (unsigned long long)(nfull + (ragged ? 1 : 0)));
+            if (halfp)
+                hmine = atomicAdd(&hcnt, 1ull);
             if (b >= 0)
                 mine = atomicAdd(&cnt[b], 1ull);
         }
@@ -293,6 +315,8 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
     }
     if (threadIdx.x == 0 && fcnt)
         fbase = atomicAdd(&ctrl[C_FCUR], fcnt);
+    if (threadIdx.x == 0 && hcnt)
+        hbase = atomicAdd(&ctrl[C_HCUR], hcnt);
     __syncthreads();
     const int lsd = launches_of(P, ps);
     const int dst = ((lsd < P.passes ? lsd : P.passes) & 1) ? 1 : 0;
@@ -312,6 +336,13 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
         pc.dst = dst;
         fulls[fbase + fmine + i] = pc;
     }
+    if (halfp && hbase + hmine < (unsigned long long)P.max_half) {
+        Piece pc;
+        pc.off = o + nfull * tile;
+        pc.len = (int32_t)rest;
+        pc.dst = dst;
+        halves[hbase + hmine] = pc;
+    }
     if (nt) {
         const int64_t tf = tbase[ps] + tmine;
         for (int64_t j = 0; j < nt && tf + j < P.max_tiles; ++j)
@@ -328,11 +359,14 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(SegParams P, unsigned 
 // segments and ragged rests of more than half a tile: such a piece is padded
 // with the maximum of the order and sorted whole, and its first len outputs
 // are stored (a workgroup-uniform branch; the packed kernel at its smaller R
-// sorts a tile about half as fast).
+// sorts a tile about half as fast).  The workgroups past the full list take
+// the half list two pieces at a time: each padded to half a tile, sorted with
+// one LDS merge level less, so the two halves stay independent runs.
 template <int R, int NT, typename T>
 __global__ __launch_bounds__(NT) void seg_full_kernel(int wave_levels, int lds_levels,
                                                       const unsigned long long *ctrl,
                                                       const Piece *__restrict__ fulls,
+                                                      const Piece *__restrict__ halves,
                                                       const int32_t *__restrict__ ik,
                                                       const int32_t *__restrict__ iv,
                                                       int32_t *__restrict__ ok,
@@ -346,10 +380,48 @@ __global__ __launch_bounds__(NT) void seg_full_kernel(int wave_levels, int lds_l
     const int lane = t & 63;
     const int wave = t >> 6;
     const int64_t nfull = (int64_t)ctrl[C_FULL];
+    if ((int64_t)blockIdx.x >= nfull) {  // two half-list pieces
+        constexpr int HT = TILE / 2;
+        const int64_t nhalf = (int64_t)ctrl[C_HALF];
+        const int64_t h = 2 * ((int64_t)blockIdx.x - nfull);
+        if (h >= nhalf)
+            return;
+        const Piece p0 = halves[h];
+        Piece p1 = p0;
+        p1.len = 0;
+        if (h + 1 < nhalf)
+            p1 = halves[h + 1];
+        // waves 0 .. NT/128 - 1 hold the first half, the others the second
+        const bool second = wave >= NT / 128;
+        const int64_t off = second ? p1.off : p0.off;
+        const int len = second ? p1.len : p0.len;
+        const int rel = (wave & (NT / 128 - 1)) * (64 * R) + lane;
+        T v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int p = rel + 64 * j;
+            v[j] = p < len ? load_elem<T>(ik + off, sizeof(T) == 8 ? iv + off : nullptr, p)
+                           : Traits<T>::kMax;
+        }
+        sort_tile_core<R, NT>(S, v, t, wave_levels, lds_levels - 1);
+        const T *zt = S + LdsSkew<T>::pos(t);
+        constexpr int ZS = LdsSkew<T>::size(NT);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            // element t + NT*j: the second half from j = R/2 on (uniform)
+            const bool sj = NT * j >= HT;
+            const int64_t po = sj ? p1.off : p0.off;
+            const int pl = sj ? p1.len : p0.len;
+            const bool scr = (sj ? p1.dst : p0.dst) != 0;
+            const int e = t + NT * j - (sj ? HT : 0);
+            if (e < pl)
+                store_elem<T>((scr ? sk : ok) + po, sizeof(T) == 8 ? (scr ? sv : ov) + po : nullptr,
+                              e, zt[ZS * j]);
+        }
+        return;
+    }
     {
         const int64_t q = blockIdx.x;  // one piece per workgroup
-        if (q >= nfull)
-            return;
         const Piece pc = fulls[q];
         // the piece's arrays from its first key on: 32-bit indices below
         const int32_t *pk = ik + pc.off;
@@ -449,7 +521,7 @@ void seg_block_kernel(SegParams P, unsigned long long *ctrl,
         const int slots = 1 << (P.tile_log2 - xlog);
         const unsigned long long first = ctrl[C_BASE + b] + (ticket - ctrl[C_TASK + b]) * slots;
         const unsigned long long avail = ctrl[C_CNT + b] - (ticket - ctrl[C_TASK + b]) * slots;
-        const int npieces = (int)(avail < slots ? avail : slots);
+        const int npieces = (int)(avail < (unsigned long long)slots ? avail : (unsigned long long)slots);
         if (t < npieces) {
             const Piece pc = pieces[first + t];
             s_off[t] = pc.off;
@@ -576,16 +648,18 @@ SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool 
     SegLayout L{};
     const int64_t tile = (int64_t)R * NT;
     const int64_t max_pieces = nseg + 2 * (n_total / tile) + 2;
-    // full pieces and padded pieces of more than half a tile, all disjoint
+    // full pieces and padded pieces of more than half a tile, all disjoint;
+    // the half list: pieces of more than a quarter of a tile
     const int64_t max_full = 2 * (n_total / tile) + 2;
+    const int64_t max_half = 4 * (n_total / tile) + 2;
     const int64_t max_tiles = n_total / TM + n_total / tile + 2;
     int64_t o = 0;
     L.ctrl = o;
     o += a256(C_WORDS * 8);
     L.pieces = o;
     o += a256(max_pieces * (int64_t)sizeof(Piece));
-    L.fulls = o;
-    o += a256(max_full * (int64_t)sizeof(Piece));
+    L.fulls = o;  // the full list, then the half list
+    o += a256((max_full + max_half) * (int64_t)sizeof(Piece));
     L.tiles = o;
     o += a256(max_tiles * 8);
     L.cr = o;
@@ -609,6 +683,7 @@ SegLayout seg_layout(int64_t n_total, int64_t nseg, int R, int NT, int TM, bool 
     L.max_tiles = max_tiles;
     L.max_pieces = max_pieces;
     L.max_full = max_full;
+    L.max_half = max_half;
     return L;
 }
 
@@ -651,36 +726,38 @@ static hipError_t launch_seg_merge(const SegMap &map, int64_t run, const int64_t
 
 template <int R, int NT, typename T>
 static hipError_t launch_seg_full(const unsigned long long *ctrl, const Piece *fulls,
-                                  int64_t max_full, const SegArgs &a, int32_t *sk, int32_t *sv,
-                                  hipStream_t s)
+                                  int64_t max_full, int64_t max_half, const SegArgs &a,
+                                  int32_t *sk, int32_t *sv, hipStream_t s)
 {
-    // one workgroup per possible full piece; those past the count exit
-    const int64_t grid = max_full;
+    // one workgroup per possible full-list piece and per possible pair of
+    // half-list pieces; those past the counts exit
+    const int64_t grid = max_full + (max_half + 1) / 2;
     const int lanes_log2 = NT == 256 ? 8 : NT == 512 ? 9 : 10;
     hipLaunchKernelGGL((seg_full_kernel<R, NT, T>), dim3((unsigned)grid), dim3(NT), 0, s, 6,
-                       lanes_log2 - 6, ctrl, fulls, a.kin, a.vin, a.kout, a.vout, sk, sv);
+                       lanes_log2 - 6, ctrl, fulls, fulls + max_full, a.kin, a.vin, a.kout, a.vout,
+                       sk, sv);
     return hipGetLastError();
 }
 
 // The full-piece kernel's shape for a tile of `tile` keys: 32 keys per lane
 // where the tile has at least 256 lanes of them, else fewer.
 static hipError_t launch_seg_full_any(int64_t tile, bool pairs, const unsigned long long *ctrl,
-                                      const Piece *fulls, int64_t max_full, const SegArgs &a,
-                                      int32_t *sk, int32_t *sv, hipStream_t s)
+                                      const Piece *fulls, int64_t max_full, int64_t max_half,
+                                      const SegArgs &a, int32_t *sk, int32_t *sv, hipStream_t s)
 {
     if (pairs) {
         switch (tile) {
-        case 2048: return launch_seg_full<8, 256, int64_t>(ctrl, fulls, max_full, a, sk, sv, s);
-        case 4096: return launch_seg_full<16, 256, int64_t>(ctrl, fulls, max_full, a, sk, sv, s);
-        case 8192: return launch_seg_full<16, 512, int64_t>(ctrl, fulls, max_full, a, sk, sv, s);
-        case 16384: return launch_seg_full<16, 1024, int64_t>(ctrl, fulls, max_full, a, sk, sv, s);
+        case 2048: return launch_seg_full<8, 256, int64_t>(ctrl, fulls, max_full, max_half, a, sk, sv, s);
+        case 4096: return launch_seg_full<16, 256, int64_t>(ctrl, fulls, max_full, max_half, a, sk, sv, s);
+        case 8192: return launch_seg_full<16, 512, int64_t>(ctrl, fulls, max_full, max_half, a, sk, sv, s);
+        case 16384: return launch_seg_full<16, 1024, int64_t>(ctrl, fulls, max_full, max_half, a, sk, sv, s);
         }
     } else {
         switch (tile) {
-        case 2048: return launch_seg_full<8, 256, int32_t>(ctrl, fulls, max_full, a, sk, sv, s);
-        case 4096: return launch_seg_full<16, 256, int32_t>(ctrl, fulls, max_full, a, sk, sv, s);
-        case 8192: return launch_seg_full<32, 256, int32_t>(ctrl, fulls, max_full, a, sk, sv, s);
-        case 16384: return launch_seg_full<32, 512, int32_t>(ctrl, fulls, max_full, a, sk, sv, s);
+        case 2048: return launch_seg_full<8, 256, int32_t>(ctrl, fulls, max_full, max_half, a, sk, sv, s);
+        case 4096: return launch_seg_full<16, 256, int32_t>(ctrl, fulls, max_full, max_half, a, sk, sv, s);
+        case 8192: return launch_seg_full<32, 256, int32_t>(ctrl, fulls, max_full, max_half, a, sk, sv, s);
+        case 16384: return launch_seg_full<32, 512, int32_t>(ctrl, fulls, max_full, max_half, a, sk, sv, s);
         }
     }
     return hipErrorInvalidValue;
@@ -732,6 +809,7 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
     P.max_pieces = L.max_pieces;
     P.max_tiles = L.max_tiles;
     P.max_full = L.max_full;
+    P.max_half = L.max_half;
     P.tile_log2 = tile_log2;
     P.r_log2 = r_log2;
     P.nb = tile_log2 - r_log2 + 1;
@@ -753,12 +831,12 @@ hipError_t launch_segmented(const SegArgs &a, hipStream_t s)
     hipLaunchKernelGGL(seg_count_kernel, dim3(sb), dim3(256), 0, s, P, ctrl);
     hipLaunchKernelGGL(seg_plan_kernel, dim3(1), dim3(64), 0, s, P, ctrl);
     hipLaunchKernelGGL(seg_scatter_kernel, dim3(sb), dim3(256), 0, s, P, ctrl, pieces, fulls,
-                       tiles, passes);
+                       fulls + L.max_full, tiles, passes);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
 
-    e = launch_seg_full_any(tile, pairs, ctrl, fulls, L.max_full, a, sk, sv, s);
+    e = launch_seg_full_any(tile, pairs, ctrl, fulls, L.max_full, L.max_half, a, sk, sv, s);
     if (e != hipSuccess)
         return e;
     e = launch_seg_block_any(a.R, a.NT, pairs, P, ctrl, pieces, a, sk, sv, s);

@@ -497,14 +497,16 @@ def test_four_way_learned_corank_segments():
 @pytest.mark.parametrize("ways", [2, 4])
 @pytest.mark.parametrize("dist", ["uniform", "sorted", "distinct16"])
 def test_pieces_around_half_a_tile(pairs, ways, dist):
-    # segments, and ragged rests of longer segments, at the half-tile line:
-    # up to half a tile they go to the packed kernel, above it (padded with
-    # the maximum) to the full-piece kernel; a tile of 4096 keys
-    T, H = 4096, 2048
+    # segments, and ragged rests of longer segments, at the quarter- and
+    # half-tile lines: up to a quarter of a tile they go to the packed
+    # kernel, up to half a tile two to a full-kernel tile (each padded to
+    # half a tile), above it one to a tile (padded); a tile of 4096 keys.
+    # An odd number of half-list pieces leaves one pair with one piece.
+    T, H, Q = 4096, 2048, 1024
     sizes = []
-    for r in (H - 1, H, H + 1, H + 2, T - 1, T):
+    for r in (Q - 1, Q, Q + 1, H - 1, H, H + 1, H + 2, T - 1, T):
         sizes += [r, T + r, 3 * T + r, 8 * T + r]
-    sizes += [T + 1, 2 * T, 5 * T + H + 1, 0, 1, H + 1]
+    sizes += [T + 1, 2 * T, 5 * T + H + 1, 0, 1, H + 1, Q + 7]
     _say("pieces around half a tile", pairs, ways, dist)
     _run(sizes, dist=dist, seed=17, pairs=pairs,
          opts={"keys_per_lane": 8, "block_threads": 512, "merge_tile": 4096,
