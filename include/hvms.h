@@ -329,21 +329,25 @@ int hvms_corank_i32(const int32_t *d_a, int64_t m, const int32_t *d_b, int64_t k
  *   d_offsets  DEVICE array of nseg+1 nondecreasing int64 offsets.
  *   n_total    must equal off[nseg] (the arrays hold at least n_total keys).
  *   max_seg    host-side upper bound on the largest segment, or negative if
- *              none is known.  It fixes how many merge passes are enqueued:
- *              ceil(log2(ceil(max_seg / block tile))), from n_total when
- *              negative (a few empty launches more).  A segment larger than
- *              the bound is NOT fully sorted: it comes out as a permutation
- *              of its input made of sorted runs of block tile * 2^passes keys,
- *              and it is counted in status word 0 (hvms_segmented_status).
+ *              none is known.  It fixes how many merge launches are enqueued:
+ *              L = ceil(log2(ceil(max_seg / block tile))) merge levels, one
+ *              launch per level (two-way) or per two levels (four-way), from
+ *              n_total when negative (a few empty launches more).  A segment
+ *              larger than the bound is NOT fully sorted: it comes out as a
+ *              permutation of its input made of sorted runs of block tile *
+ *              2^(levels merged) keys, and it is counted in status word 0
+ *              (hvms_segmented_status).
  *   d_out      16-byte aligned (pairs: d_vals_out too).
  * Elements outside [off[0], off[nseg]) are not written.  A segment whose
  * offsets fall outside [0, n_total] or decrease is treated as empty and
  * counted in status word 1.  If the sizes add up to more than n_total
  * allows, nothing is sorted or written and status word 2 is set.
- * Everything up to the block tile is sorted by one persistent launch that
- * pulls packed tasks from an atomic ticket; larger segments add one co-rank
- * and one merge launch per merge pass.  The call allocates and synchronises
- * nothing, so it can be captured into a hipGraph.  Workspace:
+ * The block stage takes two launches: one sorts the full block tiles of long
+ * segments and, padded, every segment or ragged rest of more than a quarter
+ * of a tile (one or two to a tile); a persistent one sorts the shorter ones,
+ * packed into tiles it pulls from an atomic ticket.  Larger segments add a
+ * co-rank and a merge launch per merge launch.  The call allocates and
+ * synchronises nothing, so it can be captured into a hipGraph.  Workspace:
  * hvms_segmented_workspace_bytes.
  */
 int64_t hvms_segmented_workspace_bytes(int64_t n_total, int64_t nseg, int64_t max_seg,

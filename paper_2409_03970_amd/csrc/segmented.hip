@@ -5,24 +5,29 @@
 // Plan (all kernels on the caller's stream; no memset, no allocation, no host
 // synchronisation, so the whole call can be captured into a hipGraph):
 //  1. init:     zero the control block.
-//  2. count:    each segment gets a size class.  A segment of s <= TILE keys
-//               goes to bucket X = max(R, 2^ceil(log2 s)); a larger segment is
-//               cut into ceil(s/TILE) pieces of bucket TILE and needs
-//               P_s = ceil(log2(pieces)) merge passes.  Counts are reduced in
+//  2. count:    each segment gets a size class.  A segment longer than TILE
+//               keys is cut into its full TILE-key pieces and a ragged rest,
+//               and needs P_s = ceil(log2(pieces)) merge levels.  A segment
+//               of at most TILE keys, or a rest, of s keys goes to the
+//               full-piece list if s > TILE/2 (padded), to the half list if
+//               s > TILE/4 (two to a tile), else to bucket X = max(R,
+//               2^ceil(log2 s)) of the packed kernel.  Counts are reduced in
 //               LDS, then added to the control block once per workgroup.
 //  3. plan:     one workgroup turns counts into list bases, task numbers
 //               (a task packs TILE/X pieces of one bucket into one tile) and
 //               the tile count of every merge pass.
-//  4. scatter:  pieces go to their bucket lists; the merge tiles of large
-//               segments go to a tile list ordered by P_s descending, so the
-//               tiles of pass p are a prefix of it.
-//  5. block:    persistent kernel; workgroups pull tasks with an atomic
-//               ticket, largest buckets first.  A task gathers its pieces
-//               into LDS (padded with the maximum), sorts every run of X in
-//               place (column sort, cross-lane levels, LDS merges), and
-//               scatters them back: small segments straight to the output,
-//               pieces of large segments to output or scratch by the parity
-//               of P_s.
+//  4. scatter:  pieces go to their lists; the merge tiles of large segments
+//               go to a tile list ordered by P_s descending, so the tiles of
+//               pass p are a prefix of it.
+//  5. block:    the full-piece kernel sorts the full list (one piece per
+//               workgroup) and the half list (two per workgroup); the packed
+//               kernel, persistent, pulls tasks with an atomic ticket, largest
+//               buckets first: a task gathers its pieces into LDS (padded
+//               with the maximum), sorts every run of X in place (column
+//               sort, cross-lane levels, LDS merges), and scatters them back.
+//               Short segments go straight to the output, pieces of large
+//               segments to output or scratch by the parity of their merge
+//               launches.
 //  6. passes:   for p < P_max: co-ranks of pass p's tiles, then the
 //               persistent pipelined merge over the same tile list.  With
 //               four-way passes a segment takes ceil(L_s / 2) launches for
