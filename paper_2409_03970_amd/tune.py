@@ -67,15 +67,18 @@ def candidates(op):
     if op == "sort":
         shapes.append((32, 1024))
     out = []
-    for (R, NT), K, TM, V, W in itertools.product(shapes, (6, 5, 4), (4096, 8192, 16384), (2, 3),
-                                                  (2, 4)):
+    pair_op = op in ("sort_pairs", "segmented_pairs")
+    for (R, NT), K, TM, V, W in itertools.product(shapes, (6, 5, 4), (2048, 4096, 8192, 16384),
+                                                  (2, 3), (2, 4)):
         if TM > 2 * R * NT:
             continue
         if TM == 16384 and (op != "sort" or W != 4):  # four-way key passes only
             continue
+        if TM == 2048 and not (pair_op and W == 4):  # four-way pair passes only
+            continue
         if op != "sort" and R * NT * 8 > 163840:
             continue
-        if W == 4 and (V == 3 or (op in ("sort_pairs", "segmented_pairs") and TM != 4096)):
+        if W == 4 and (V == 3 or (pair_op and TM not in (2048, 4096))):
             continue
         if op == "segmented_pairs" and (R, NT) == (16, 1024):  # pair tile + piece table > LDS
             continue

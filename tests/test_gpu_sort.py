@@ -312,6 +312,25 @@ def test_full_size_2pow28(dist):
             assert np.array_equal(y.cpu().numpy(), want)
 
 
+def test_full_size_pairs_2pow28():
+    # the key-value sort in its tuned launch shape for 2^28 pairs (four-way
+    # passes); values are the input indices, so the (key, value) order is
+    # unique: keys element by element against the oracle, values a
+    # permutation that ascends within every run of equal keys and points
+    # back at its key
+    n = 1 << 28
+    _say("full size pairs")
+    xs, want = expected_2p28("uniform")
+    k = torch.from_numpy(xs).to(DEV)
+    v = torch.arange(n, dtype=torch.int32, device=DEV)
+    ko, vo = hv.sort_pairs(k, v)
+    torch.cuda.synchronize()
+    assert np.array_equal(ko.cpu().numpy(), want)
+    assert bool(torch.equal(k[vo.long()], ko))
+    assert bool(((ko[1:] > ko[:-1]) | (vo[1:] > vo[:-1])).all())
+    assert bool(torch.equal(torch.sort(vo).values, v))
+
+
 @pytest.mark.parametrize("ways", [2, 4])
 def test_beyond_2pow31_keys(ways):
     # more keys than a 32-bit index reaches (8.6 GB), ragged: every index,
