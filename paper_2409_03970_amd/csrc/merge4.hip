@@ -853,8 +853,9 @@ hipError_t launch_merge4_pass(int tm, bool pairs, const int32_t *kin, const int3
     case 2048:
         return pairs ? launch_m4<256, 8, int64_t>(kin, vin, kout, vout, n, run, rec, occupancy, s, xout)
                      : hipErrorInvalidValue;
-    case 4096:
-        return pairs ? launch_m4<256, 16, int64_t>(kin, vin, kout, vout, n, run, rec, occupancy, s, xout)
+    case 4096:  // pairs: 512 threads x 8 (64-bit LDS tiles: the VGPRs of 8 outputs keep
+                // four waves per SIMD, as many as the tile's LDS allows)
+        return pairs ? launch_m4<512, 8, int64_t>(kin, vin, kout, vout, n, run, rec, occupancy, s, xout)
                      : launch_m4<256, 16, int32_t>(kin, vin, kout, vout, n, run, rec, occupancy, s, xout);
     case 8192:
         return pairs ? hipErrorInvalidValue
@@ -911,7 +912,7 @@ hipError_t launch_seg_merge4(int tm, bool pairs, const SegMap &map, int64_t run,
     case 2048:
         return launch_m4_seg<256, 8, int64_t>(map, n_total, run, rec, obase, max_tiles, occupancy, s);
     case 4096:
-        return pairs ? launch_m4_seg<256, 16, int64_t>(map, n_total, run, rec, obase, max_tiles, occupancy, s)
+        return pairs ? launch_m4_seg<512, 8, int64_t>(map, n_total, run, rec, obase, max_tiles, occupancy, s)
                      : launch_m4_seg<256, 16, int32_t>(map, n_total, run, rec, obase, max_tiles, occupancy, s);
     case 8192:
         return launch_m4_seg<512, 16, int32_t>(map, n_total, run, rec, obase, max_tiles, occupancy, s);
