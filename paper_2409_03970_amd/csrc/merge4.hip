@@ -247,6 +247,11 @@ __device__ __forceinline__ void select4(const SelWin<T> (&S)[4], int64_t D, int6
 // Co-ranks (x, a, c) of diagonal d of X (+) Y: the shares of A, B, C and D
 // among the d smallest elements of the group, selected in the four whole
 // runs (x = a + b: X's share).
+// When the four runs' ranges do not overlap in run order (presorted input)
+// or in reverse run order (reverse-sorted input, or each run one value), the
+// merge is their concatenation in that order and the shares follow from d
+// directly: one round of reads of the runs' end elements (shared by all
+// tiles of a group) instead of the selection.
 template <typename T>
 __device__ __forceinline__ Quad quad_corank(const Group<T> &G, int64_t d, unsigned &probes)
 {
@@ -255,8 +260,52 @@ __device__ __forceinline__ Quad quad_corank(const Group<T> &G, int64_t d, unsign
     S[1] = SelWin<T>{G.X.qk, G.X.qv, G.X.nq};
     S[2] = SelWin<T>{G.Y.pk, G.Y.pv, G.Y.np};
     S[3] = SelWin<T>{G.Y.qk, G.Y.qv, G.Y.nq};
+    using E = SelE<T>;
+    E first[4], last[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        first[r] = S[r].at(r, 0);  // an empty run's reads are sentinels (no load)
+        last[r] = S[r].W > 0 ? S[r].at(r, S[r].W - 1) : S[r].sentinel(r);
+    }
+    ++probes;
+    bool up = true, down = true, hu = false, hd = false;
+    E lu = first[0], ld = first[0];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)  // every element of an earlier run before every later one
+        if (S[r].W > 0) {
+            if (hu)
+                up = up && sel_less(lu, first[r]);
+            lu = last[r];
+            hu = true;
+        }
+#pragma unroll
+    for (int r = 3; r >= 0; --r)  // ... or of a later run before every earlier one
+        if (S[r].W > 0) {
+            if (hd)
+                down = down && sel_less(ld, first[r]);
+            ld = last[r];
+            hd = true;
+        }
     int64_t w[4];
-    select4<T>(S, d, w, probes);
+    if (up || down) {
+        int64_t rem = d;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r = up ? k : 3 - k;
+            int64_t take = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (q == r)
+                    take = rem < S[q].W ? rem : S[q].W;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (q == r)
+                    w[q] = take;
+            rem -= take;
+        }
+    } else {
+        select4<T>(S, d, w, probes);
+    }
     return Quad{w[0] + w[1], w[0], w[2]};
 }
 

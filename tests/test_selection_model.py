@@ -109,3 +109,49 @@ def test_selection_rounds_are_logarithmic():
         assert 13 <= rounds <= 2 * 13
         total += rounds
     assert total / 20 < 1.6 * 13
+
+
+def corank_model(runs, d):
+    """The four-way co-rank as the kernel takes it: if the runs' ranges do
+    not overlap in run order, or in reverse run order, the shares fill the
+    runs in that order; else the selection."""
+    def first(r):
+        return _at(runs, r, 0)
+
+    def last(r):
+        return _at(runs, r, len(runs[r]) - 1) if runs[r] else _at(runs, r, 0)
+    nonempty = [r for r in range(4) if runs[r]]
+    up = all(last(a) < first(b) for a, b in zip(nonempty, nonempty[1:]))
+    rev = nonempty[::-1]
+    down = all(last(a) < first(b) for a, b in zip(rev, rev[1:]))
+    if up or down:
+        w, rem = [0] * 4, d
+        for r in (range(4) if up else range(3, -1, -1)):
+            w[r] = min(rem, len(runs[r]))
+            rem -= w[r]
+        return w
+    return select_model(runs, d)[0]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_disjoint_runs_fast_path_matches_brute_force(seed):
+    rng = random.Random(100 + seed)
+    for _ in range(400):
+        kind = rng.choice(["up", "down", "equal", "random", "touching"])
+        lens = [rng.choice([0, 1, 2, 5, 16, rng.randrange(0, 60)]) for _ in range(4)]
+        if kind == "up":        # presorted: run r holds keys above run r - 1's
+            runs = [sorted(rng.randrange(100 * r, 100 * r + 100) for _ in range(n))
+                    for r, n in enumerate(lens)]
+        elif kind == "down":    # reverse-sorted: run r holds keys below run r - 1's
+            runs = [sorted(rng.randrange(400 - 100 * r, 500 - 100 * r) for _ in range(n))
+                    for r, n in enumerate(lens)]
+        elif kind == "equal":   # one value everywhere: ties broken by run
+            runs = [[7] * n for n in lens]
+        elif kind == "touching":  # neighbouring runs share their boundary key
+            runs = [sorted([10 * r] * (n // 2) + [10 * (r + 1)] * (n - n // 2))
+                    for r, n in enumerate(lens)]
+        else:
+            runs = [sorted(rng.randrange(50) for _ in range(n)) for n in lens]
+        n = sum(lens)
+        for d in sorted({0, n, rng.randrange(n + 1), rng.randrange(n + 1)}):
+            assert corank_model(runs, d) == brute(runs, d), (kind, runs, d)
